@@ -1,0 +1,55 @@
+"""The CPU oracle against closed forms, an exact ODE solution, quadrature,
+symmetry and invariance (no GPU)."""
+import pytest
+
+import oracle_pins as P
+
+
+@pytest.mark.parametrize("name", sorted(P.ALL))
+def test_pin(name):
+    fn, tol = P.ALL[name]
+    err = fn()
+    assert err <= tol, f"{name}: {err:.3e} > {tol:.0e}"
+
+
+def test_stack_converges_with_order():
+    """Truncated solve -> exact continuum field at O(M^-3) (tangential E is
+    continuous, so the plain Toeplitz product converges fast for it)."""
+    e = [P.err_stack_exact(m, '1d') for m in (10, 20, 40)]
+    assert e[1] < e[0] / 5 and e[2] < e[1] / 5
+
+
+def test_eps_zz_laurent_trend():
+    """eps_zz of a stack (k || z) equals 1/[T^-1]_00 and approaches the
+    quasi-static 1/<1/eps> only slowly (the factorisation caveat of the
+    truncation section)."""
+    import numpy as np
+    from oracle import gsm as O
+    from paper_1501_01752_amd import inputs
+    vox = inputs.layered_stack(64, 0.375, 2.25, 9.0)
+    target = 1.0 / np.mean(1.0 / vox)
+    prev = None
+    for mz in (5, 10, 20):
+        ee = P.eps_eff_case(vox, (1, 1, mz), eps_b=3.0)[0]
+        c = O.box_image(vox, (0, 0, 2 * mz))[:, 0, 0]
+        m = np.arange(-mz, mz + 1)
+        T = c[(m[:, None] - m[None, :]) + 2 * mz]
+        assert abs(ee[2, 2] - 1.0 / np.linalg.inv(T)[mz, mz]) < 1e-12
+        d = abs(ee[2, 2] - target)
+        assert prev is None or d < prev
+        prev = d
+
+
+def test_maxwell_garnett_scalars_reproduce():
+    """The paper's printed quasi-static indices follow from the filling
+    factors it states (air spheres of radius Lambda/3 in n = 1.5):
+    f = 0.155 -> 1.4213 (uniaxial case), f = 0.141 -> 1.4284 (biaxial case).
+    This pins the geometry reading only, not the solver."""
+    import numpy as np
+    f_uni = 4.0 / 3.0 * np.pi / 27.0
+    f_bi = f_uni / 1.1
+    assert round(f_uni, 3) == 0.155 and round(f_bi, 3) == 0.141
+    em, ei = 2.25, 1.0
+    for f, ref in ((0.155, 1.4213), (0.141, 1.4284)):
+        e = em * (ei + 2 * em + 2 * f * (ei - em)) / (ei + 2 * em - f * (ei - em))
+        assert abs(np.sqrt(e) - ref) < 1e-4
