@@ -1,0 +1,236 @@
+/*
+ * gsm.h - C ABI of libgsm: the Generalized Source Method (GSM) solve for 3D
+ * periodic dielectric composites on AMD Instinct MI355X (gfx950).
+ *
+ * Method: A. A. Shcherbakov, A. V. Tishchenko, "3D periodic dielectric
+ * composite homogenization based on the Generalized Source Method",
+ * arXiv 1501.01752.  The library solves the truncated Fourier-space system of
+ * the paper's Eq.(4),
+ *
+ *   E_am - sum_b G_ab(k_m) sum_m' (Delta eps / eps_b)_{m-m'} E_bm' = E^inc_am,
+ *   G_ab(k) = (k_b^2 delta_ab - k_a k_b) / (|k|^2 - k_b^2),  k_b^2 = k0^2 eps_b,
+ *   k_m = k_inc + (m_x K_x, m_y K_y, m_z K_z),  K_a = 2 pi / Lambda_a,
+ *   E^inc_am = delta_m0 a_a,
+ *
+ * with a restarted Krylov method (GMRES, the method the paper settles on in
+ * its "Calculation details" section) whose matrix-vector product applies the
+ * Toeplitz contrast matrix by FFT (the "heaviest procedure" of the truncation
+ * section): inverse 3D FFT of the three field components, point-wise product
+ * with the band-limited contrast on the real-space grid, forward 3D FFT, then
+ * the per-harmonic 3x3 Green tensor.  All of it runs in HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Per-axis arrays are ordered (x, y, z).  Lengths use any one unit:
+ *   period, wavelength and 1/|k_inc| must agree.  k0 = 2 pi / wavelength.
+ * - Voxel permittivities: real, Vz*Vy*Vx values, x fastest; voxel
+ *   (ix, iy, iz) fills [ix, ix+1) x [iy, iy+1) x [iz, iz+1) in units of
+ *   Lambda_a / V_a.  The plan takes the exact Fourier image of this
+ *   piecewise-constant body (the paper prefers exact Fourier images to mesh
+ *   samples, "Calculation details").
+ * - Field vectors ("systems"): one per (instance, drive), in instance order
+ *   and drive order; each is 3 * N1z * N1y * N1x complex128 values
+ *   (interleaved re, im) laid out [component][mz][my][mx] with index
+ *   m_a + M_a, N1_a = 2 M_a + 1.  Systems are concatenated without padding.
+ * - Device pointers are HIP device memory of the plan's device unless a
+ *   GSM_OUT_HOST flag says otherwise.  `stream` is a hipStream_t (NULL: the
+ *   default stream).  Calls returning results synchronise that stream
+ *   before they return.
+ * - No call throws or aborts; every failure is a negative status and
+ *   gsm_last_error() (thread-local) holds a message.  On error the outputs
+ *   are left untouched, except GSM_W_* results, which are written.
+ * - A plan is used by one host thread / stream at a time.
+ */
+#ifndef GSM_H
+#define GSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSM_VERSION 100
+
+/* status codes */
+enum {
+  GSM_OK = 0,
+  GSM_W_NOT_CONVERGED = 1, /* tolerance not met within the caps; best iterate returned */
+  GSM_E_ARG = -1,          /* invalid argument (sizes, pointers, ranges) */
+  GSM_E_NONFINITE = -2,    /* NaN or Inf in an input */
+  GSM_E_NOMEM = -3,        /* device allocation failed */
+  GSM_E_DEVICE = -4,       /* HIP runtime error or no device */
+  GSM_E_SINGULAR = -5,     /* |k_m|^2 too close to k_b^2 for some m, or singular E0 */
+  GSM_E_WORKSPACE = -6,    /* workspace pointer NULL or smaller than gsm_workspace_size */
+  GSM_E_UNSUPPORTED = -7   /* order count beyond the largest supported FFT grid */
+};
+
+/* precision of the Krylov iterations (the FP64 residual is always FP64) */
+enum { GSM_MIXED = 0, GSM_FP64 = 1 };
+/* Krylov method */
+enum { GSM_GMRES = 0 };
+/* gsm_solver_opts.flags */
+enum { GSM_OUT_HOST = 1 /* E_out / eps_eff / grad are host pointers */ };
+/* gsm_apply modes */
+enum { GSM_APPLY_FORWARD = 0, GSM_APPLY_ADJOINT = 1 };
+
+typedef struct gsm_plan_s* gsm_plan_t;
+
+/* Geometry of one unit cell (the periodic permittivity of the section on
+ * artificial dielectric structures): periods and a voxel body. */
+typedef struct gsm_geometry {
+  double period[3];  /* Lambda_x, Lambda_y, Lambda_z > 0 (orthogonal lattice) */
+  int32_t nvox[3];   /* Vx, Vy, Vz >= 1 */
+  const double* eps; /* host, Vz*Vy*Vx real values > 0, x fastest; copied */
+} gsm_geometry;
+
+typedef struct gsm_plan_opts {
+  int32_t m_max[3]; /* largest order count M_a any instance will use (0..31) */
+  int32_t device;   /* HIP device ordinal */
+  int32_t flags;    /* reserved, must be 0 */
+  int32_t reserved;
+} gsm_plan_opts;
+
+/* One (omega, k) point.  Harmonics m_a run over [-M_a, M_a] (the paper's
+ * truncation to N_a = 2 M_a + 1 harmonics per axis). */
+typedef struct gsm_instance {
+  double wavelength; /* lambda > 0 */
+  double k_inc[3];   /* incident Bloch wave-vector k^inc (absolute; |k^inc| = n_i k0) */
+  int32_t M[3];      /* order counts, 0 <= M_a <= plan m_max[a] */
+  int32_t n_drive;   /* number of drives 1..3 (gsm_eff_tensor ignores it and uses 3) */
+  double pol[3][6];  /* drive d: incident amplitude a (re, im of x, y, z) */
+  double eps_b;      /* basis permittivity; <= 0 selects the policy below */
+} gsm_instance;
+
+typedef struct gsm_solver_opts {
+  double tol;         /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64); default 1e-9 */
+  double inner_tol;   /* GSM_MIXED: residual reduction asked of each FP32 Krylov
+                         cycle; default 1e-5 */
+  int32_t restart;    /* Krylov dimension per cycle, 1..64; default 30 */
+  int32_t max_iter;   /* cap on Krylov iterations per system; default 5000 */
+  int32_t max_refine; /* cap on FP64 residual evaluations per system; default 200 */
+  int32_t precision;  /* GSM_MIXED (complex64 Krylov inside FP64 refinement) or GSM_FP64 */
+  int32_t method;     /* GSM_GMRES */
+  int32_t flags;      /* GSM_OUT_HOST */
+  const double* x0;   /* NULL or an initial guess (device, layout of E_out) */
+} gsm_solver_opts;
+
+/* Result of one system (instance, drive). */
+typedef struct gsm_solve_info {
+  int32_t status;      /* GSM_OK, GSM_W_NOT_CONVERGED, GSM_E_SINGULAR */
+  int32_t iterations;  /* Krylov iterations (matrix-vector products in the Krylov precision) */
+  int32_t refinements; /* FP64 residual evaluations */
+  int32_t fft_size;    /* P, the FFT grid per axis */
+  double rel_residual; /* final ||b - A x||_2 / ||b||_2 evaluated in FP64 */
+  double eps_b;        /* basis permittivity used */
+} gsm_solve_info;
+
+/* ---------------------------------------------------------------- helpers */
+
+int gsm_version(void);
+const char* gsm_strerror(int status);
+const char* gsm_last_error(void); /* thread-local message of the last failure */
+
+/* Fill opts with the defaults listed above. */
+void gsm_solver_opts_default(gsm_solver_opts* opts);
+
+/* FFT grid size P used for order counts M (the smallest supported size with
+ * P >= 4 max_a M_a + 1, the condition under which the cropped FFT product
+ * equals the truncated Toeplitz product).  Returns P > 0, or GSM_E_UNSUPPORTED. */
+int gsm_fft_size(const int32_t M[3]);
+
+/* CPU-only validation of a geometry, plan options and instances (no device
+ * call).  Checks sizes, finiteness, positivity, M ranges and drive counts,
+ * and the basis-permittivity choice (GSM_E_SINGULAR if an explicit eps_b
+ * gives min_m | |k_m|^2/k0^2 - eps_b | < 1e-3 eps_b).  Any pointer may be NULL
+ * to skip its checks (n_inst = 0 skips the instances). */
+int gsm_plan_validate(const gsm_geometry* geo, const gsm_plan_opts* opts, int32_t n_inst,
+                      const gsm_instance* inst);
+
+/* Basis permittivity the library uses for `inst` with plan `plan`: the
+ * instance's eps_b if > 0; otherwise the voxel mean <eps>, unless that comes
+ * within 1e-3 eps_b of some |k_m|^2/k0^2, in which case the value in
+ * [0.5 eps_min, 2 eps_max] with the largest such margin on a fixed scan. */
+int gsm_basis_eps(gsm_plan_t plan, const gsm_instance* inst, double* eps_b);
+
+/* ------------------------------------------------------------------ plan */
+
+/* Build a plan on opts->device: copies the voxels to the device and computes
+ * there the exact Fourier coefficients c_n, |n_a| <= 2 m_max[a], of the voxel
+ * body (voxel DFT times the box factor sinc(pi n/V) exp(-i pi n/V) per axis).
+ * Band-limited real-space contrast grids for each (M, P) are derived from c_n
+ * on first use.  The plan owns its device memory. */
+int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out);
+int gsm_plan_destroy(gsm_plan_t plan);
+
+/* Copy the plan's coefficients c_n to host memory: (4 m_max[2]+1) x
+ * (4 m_max[1]+1) x (4 m_max[0]+1) complex128, [nz][ny][nx], index n_a + 2 m_max[a]. */
+int gsm_plan_coefficients(gsm_plan_t plan, double* c_out);
+
+/* Copy the band-limited permittivity grid used for order counts M and grid
+ * P: eps_M(r_j) = sum_{|n_a| <= 2 M_a} c_n exp(2 pi i n.j / P), real,
+ * P^3 doubles [z][y][x] (host). */
+int gsm_plan_contrast_grid(gsm_plan_t plan, const int32_t M[3], int32_t P, double* g_out);
+
+/* ------------------------------------------------------------- workspace */
+
+/* Bytes of device workspace gsm_solve / gsm_eff_tensor / gsm_apply need for
+ * these instances and options (the caller allocates it, e.g. as a torch
+ * uint8 tensor, and may reuse it across calls). */
+int gsm_workspace_size(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
+                       const gsm_solver_opts* opts, size_t* bytes);
+
+/* ----------------------------------------------------------------- solve */
+
+/* Solve Eq.(4) for every (instance, drive).  Systems of equal (M, P) are
+ * batched into the same kernel launches.  E_out receives the fields
+ * (complex128, layout above); info (host, one per system) the per-system
+ * results.  Returns the worst status.  Synchronises `stream` before
+ * returning. */
+int gsm_solve(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
+              const gsm_solver_opts* opts, void* ws, size_t ws_bytes, double* E_out,
+              gsm_solve_info* info, void* stream);
+
+/* Apply the operator of Eq.(4) once: y = A x (GSM_APPLY_FORWARD) or
+ * y = A^H x (GSM_APPLY_ADJOINT), for every (instance, drive) vector, in
+ * complex128 (precision GSM_FP64) or complex64 (GSM_MIXED: x and y are then
+ * interleaved float pairs).  Device pointers.  For parity tests and timing. */
+int gsm_apply(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst, int32_t precision,
+              int32_t mode, const void* x, void* y, void* ws, size_t ws_bytes, void* stream);
+
+/* Effective permittivity tensor of each instance (field-averaged form): the
+ * three drives a = x, y, z are solved, and with E0 and D0 the zeroth Fourier
+ * orders of E and of eps E, eps_eff = D0 E0^-1 (3x3 complex128, row-major,
+ * [inst][3][3]).  Its Fresnel zeros det(|k|^2 I - k k^T - k0^2 eps_eff) = 0
+ * are the resonances the paper's pole search finds (Eqs.(6)-(10)).  E_save,
+ * if not NULL, receives the three solved fields per instance (device, layout
+ * of E_out with 3 drives per instance) for gsm_eff_tensor_vjp.  info: 3 per
+ * instance. */
+int gsm_eff_tensor(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
+                   const gsm_solver_opts* opts, double* eps_eff, double* E_save, void* ws,
+                   size_t ws_bytes, gsm_solve_info* info, void* stream);
+
+/* Adjoint solve A^H lambda = rhs for every (instance, drive); rhs and
+ * lambda_out device, layout of E_out.  A^H = I - V^H G^H applies the Green
+ * tensor before the contrast convolution (G is real symmetric for real
+ * k_inc and eps_b; V is Hermitian for real eps). */
+int gsm_solve_adjoint(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
+                      const gsm_solver_opts* opts, const double* rhs, double* lambda_out,
+                      void* ws, size_t ws_bytes, gsm_solve_info* info, void* stream);
+
+/* Vector-Jacobian product of gsm_eff_tensor with respect to the voxel
+ * permittivities: given gbar = dL/d conj(eps_eff) per instance (3x3 complex128,
+ * host) and the saved fields (device, from gsm_eff_tensor), accumulates
+ * dL/d eps_v = 2 Re sum <...> into grad_vox (device, Vz*Vy*Vx doubles).  Runs
+ * three adjoint solves per instance; eps_b is held fixed (eps_eff does not
+ * depend on it). */
+int gsm_eff_tensor_vjp(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
+                       const gsm_solver_opts* opts, const double* E_save,
+                       const double* eps_eff, const double* gbar, double* grad_vox, void* ws,
+                       size_t ws_bytes, gsm_solve_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSM_H */

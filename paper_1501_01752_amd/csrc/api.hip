@@ -1,0 +1,964 @@
+// Host side of libgsm: the C ABI declared in include/gsm.h.
+//
+// Validation, the basis-permittivity policy, grouping of (instance, drive)
+// systems by (M, P), workspace carving, and the solve loop that drives the
+// HIP kernels (FP64 residual -> Krylov cycle -> FP64 update, see refine.inc).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gsm.h"
+#include "gsm_internal.h"
+
+using namespace gsm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? GSM_E_NOMEM : GSM_E_DEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                       \
+  } while (0)
+
+constexpr int kSupportedP[] = {4, 8, 16, 32, 64, 128};
+
+int fft_size_for(const int32_t M[3]) {
+  int mm = std::max(M[0], std::max(M[1], M[2]));
+  for (int p : kSupportedP)
+    if (p >= 4 * mm + 1) return p;
+  return GSM_E_UNSUPPORTED;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Grid {
+  double* g64 = nullptr;
+  float* g32 = nullptr;
+};
+
+}  // namespace
+
+struct gsm_plan_s {
+  int device = 0;
+  double period[3]{};
+  int vox[3]{};
+  int mmax[3]{};
+  int nc[3]{};  // 4 m_max + 1
+  double eps_mean = 0, eps_min = 0, eps_max = 0;
+  double2* d_coef = nullptr;
+  std::map<std::array<int, 4>, Grid> grids;
+  int* h_flags = nullptr;  // pinned
+  int h_flags_cap = 0;
+};
+
+namespace {
+
+// ----------------------------------------------------------- validation ----
+
+int check_geometry(const gsm_geometry* geo) {
+  if (!geo) return fail(GSM_E_ARG, "geometry is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(geo->period[a])) return fail(GSM_E_NONFINITE, "period[%d] is not finite", a);
+    if (!(geo->period[a] > 0)) return fail(GSM_E_ARG, "period[%d] must be > 0", a);
+    if (geo->nvox[a] < 1 || geo->nvox[a] > 4096) return fail(GSM_E_ARG, "nvox[%d]=%d out of range", a, geo->nvox[a]);
+  }
+  if (!geo->eps) return fail(GSM_E_ARG, "eps is NULL");
+  const long long nv = (long long)geo->nvox[0] * geo->nvox[1] * geo->nvox[2];
+  if (nv > (1LL << 28)) return fail(GSM_E_ARG, "too many voxels");
+  for (long long i = 0; i < nv; ++i) {
+    if (!std::isfinite(geo->eps[i])) return fail(GSM_E_NONFINITE, "eps[%lld] is not finite", i);
+    if (!(geo->eps[i] > 0)) return fail(GSM_E_ARG, "eps[%lld] must be > 0", i);
+  }
+  return GSM_OK;
+}
+
+int check_plan_opts(const gsm_plan_opts* o) {
+  if (!o) return fail(GSM_E_ARG, "plan options are NULL");
+  for (int a = 0; a < 3; ++a)
+    if (o->m_max[a] < 0 || o->m_max[a] > kMaxOrder)
+      return fail(GSM_E_UNSUPPORTED, "m_max[%d]=%d outside [0, %d]", a, o->m_max[a], kMaxOrder);
+  if (o->flags != 0) return fail(GSM_E_ARG, "plan flags must be 0");
+  return GSM_OK;
+}
+
+int check_instance(const gsm_instance& in, const int* mmax, int i, bool need_drives) {
+  if (!std::isfinite(in.wavelength)) return fail(GSM_E_NONFINITE, "instance %d: wavelength not finite", i);
+  if (!(in.wavelength > 0)) return fail(GSM_E_ARG, "instance %d: wavelength must be > 0", i);
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(in.k_inc[a])) return fail(GSM_E_NONFINITE, "instance %d: k_inc not finite", i);
+    if (in.M[a] < 0 || in.M[a] > kMaxOrder) return fail(GSM_E_UNSUPPORTED, "instance %d: M[%d]=%d", i, a, in.M[a]);
+    if (mmax && in.M[a] > mmax[a])
+      return fail(GSM_E_ARG, "instance %d: M[%d]=%d exceeds plan m_max %d", i, a, in.M[a], mmax[a]);
+  }
+  if (!std::isfinite(in.eps_b)) return fail(GSM_E_NONFINITE, "instance %d: eps_b not finite", i);
+  if (need_drives) {
+    if (in.n_drive < 1 || in.n_drive > 3) return fail(GSM_E_ARG, "instance %d: n_drive=%d", i, in.n_drive);
+    for (int d = 0; d < in.n_drive; ++d) {
+      double nn = 0;
+      for (int c = 0; c < 6; ++c) {
+        if (!std::isfinite(in.pol[d][c])) return fail(GSM_E_NONFINITE, "instance %d: pol not finite", i);
+        nn += in.pol[d][c] * in.pol[d][c];
+      }
+      if (nn == 0) return fail(GSM_E_ARG, "instance %d: drive %d is zero", i, d);
+    }
+  }
+  return GSM_OK;
+}
+
+int check_solver_opts(const gsm_solver_opts* s) {
+  if (!s) return fail(GSM_E_ARG, "solver options are NULL");
+  if (!std::isfinite(s->tol) || !std::isfinite(s->inner_tol)) return fail(GSM_E_NONFINITE, "tolerance not finite");
+  if (s->restart < 1 || s->restart > kMaxRestart) return fail(GSM_E_ARG, "restart=%d outside [1, %d]", s->restart, kMaxRestart);
+  if (s->max_iter < 1) return fail(GSM_E_ARG, "max_iter must be >= 1");
+  if (s->max_refine < 1) return fail(GSM_E_ARG, "max_refine must be >= 1");
+  if (s->precision != GSM_MIXED && s->precision != GSM_FP64) return fail(GSM_E_ARG, "unknown precision %d", s->precision);
+  if (s->method != GSM_GMRES) return fail(GSM_E_ARG, "unknown method %d", s->method);
+  if (s->flags & ~GSM_OUT_HOST) return fail(GSM_E_ARG, "unknown solver flags");
+  return GSM_OK;
+}
+
+// -------------------------------------------------- basis permittivity ----
+
+// sorted |q_m|^2 over the truncated harmonic set
+std::vector<double> shell_values(const gsm_instance& in, const double* period) {
+  const double k0 = 2.0 * M_PI / in.wavelength;
+  double q0[3], b[3];
+  for (int a = 0; a < 3; ++a) {
+    q0[a] = in.k_inc[a] / k0;
+    b[a] = in.wavelength / period[a];
+  }
+  std::vector<double> v;
+  v.reserve((size_t)(2 * in.M[0] + 1) * (2 * in.M[1] + 1) * (2 * in.M[2] + 1));
+  for (int mz = -in.M[2]; mz <= in.M[2]; ++mz)
+    for (int my = -in.M[1]; my <= in.M[1]; ++my)
+      for (int mx = -in.M[0]; mx <= in.M[0]; ++mx) {
+        const double qx = q0[0] + mx * b[0], qy = q0[1] + my * b[1], qz = q0[2] + mz * b[2];
+        v.push_back(qx * qx + qy * qy + qz * qz);
+      }
+  std::sort(v.begin(), v.end());
+  return v;
+}
+
+double margin_of(const std::vector<double>& sorted, double eb) {
+  auto it = std::lower_bound(sorted.begin(), sorted.end(), eb);
+  double m = INFINITY;
+  if (it != sorted.end()) m = std::min(m, std::fabs(*it - eb));
+  if (it != sorted.begin()) m = std::min(m, std::fabs(*(it - 1) - eb));
+  return m;
+}
+
+constexpr double kSingularRel = 1e-3;
+
+int resolve_eps_b(const double* period, double eps_mean, double eps_min, double eps_max, const gsm_instance& in,
+                  int idx, double* out) {
+  const std::vector<double> sh = shell_values(in, period);
+  if (in.eps_b > 0) {
+    if (margin_of(sh, in.eps_b) < kSingularRel * in.eps_b)
+      return fail(GSM_E_SINGULAR, "instance %d: |k_m|^2 = k_b^2 within 1e-3 for eps_b=%g", idx, in.eps_b);
+    *out = in.eps_b;
+    return GSM_OK;
+  }
+  if (margin_of(sh, eps_mean) >= kSingularRel * eps_mean) {
+    *out = eps_mean;
+    return GSM_OK;
+  }
+  const double lo = 0.5 * eps_min, hi = 2.0 * eps_max;
+  double best = -1, best_eb = eps_mean;
+  const int n = 4001;
+  for (int i = 0; i < n; ++i) {
+    const double eb = lo + (hi - lo) * i / (n - 1);
+    const double r = margin_of(sh, eb) / eb;
+    if (r > best) {
+      best = r;
+      best_eb = eb;
+    }
+  }
+  if (best < kSingularRel) return fail(GSM_E_SINGULAR, "instance %d: no admissible eps_b", idx);
+  *out = best_eb;
+  return GSM_OK;
+}
+
+// ------------------------------------------------------------- systems ----
+
+struct SysDesc {
+  int inst, drive;
+  int M[3];
+  int P;
+  long long n;        // complex values
+  long long out_off;  // complex offset in E_out
+  SysParam par;
+};
+
+struct Group {
+  GroupShape shape{};
+  std::vector<int> sys;
+  // workspace
+  SysParam* par = nullptr;
+  SysState* st = nullptr;
+  int* flags = nullptr;
+  double2* x64 = nullptr;
+  double2* r64 = nullptr;
+  void* V = nullptr;
+  double2* T = nullptr;
+  double2* part1 = nullptr;
+  double2* part2 = nullptr;
+  double* partn = nullptr;
+  double* partc = nullptr;
+};
+
+struct SysExport {
+  int status, iters, refinements, pad;
+  double rel;
+  double2 e0[3];
+  double2 w0[3];
+};
+
+int build_systems(gsm_plan_s* plan, int n_inst, const gsm_instance* inst, const gsm_solver_opts* so,
+                  bool three_drives, std::vector<SysDesc>& sys) {
+  sys.clear();
+  long long off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const gsm_instance& in = inst[i];
+    int rc = check_instance(in, plan->mmax, i, !three_drives);
+    if (rc) return rc;
+    double eb;
+    rc = resolve_eps_b(plan->period, plan->eps_mean, plan->eps_min, plan->eps_max, in, i, &eb);
+    if (rc) return rc;
+    const int P = fft_size_for(in.M);
+    if (P < 0) return fail(GSM_E_UNSUPPORTED, "instance %d: order count too large", i);
+    const int nd = three_drives ? 3 : in.n_drive;
+    for (int d = 0; d < nd; ++d) {
+      SysDesc s{};
+      s.inst = i;
+      s.drive = d;
+      for (int a = 0; a < 3; ++a) s.M[a] = in.M[a];
+      s.P = P;
+      s.n = 3LL * (2 * in.M[0] + 1) * (2 * in.M[1] + 1) * (2 * in.M[2] + 1);
+      s.out_off = off;
+      off += s.n;
+      const double k0 = 2.0 * M_PI / in.wavelength;
+      for (int a = 0; a < 3; ++a) {
+        s.par.q0[a] = in.k_inc[a] / k0;
+        s.par.b[a] = in.wavelength / plan->period[a];
+      }
+      s.par.eps_b = eb;
+      s.par.inv_eps_b = 1.0 / eb;
+      double nn = 0;
+      for (int c = 0; c < 3; ++c) {
+        double re, im;
+        if (three_drives) {
+          re = (c == d) ? 1.0 : 0.0;
+          im = 0.0;
+        } else {
+          re = in.pol[d][2 * c];
+          im = in.pol[d][2 * c + 1];
+        }
+        s.par.a[2 * c] = re;
+        s.par.a[2 * c + 1] = im;
+        nn += re * re + im * im;
+      }
+      s.par.bnorm = std::sqrt(nn);
+      if (so) {
+        s.par.tol = so->tol;
+        s.par.inner_tol = so->inner_tol;
+        s.par.max_iter = so->max_iter;
+        s.par.max_refine = so->max_refine;
+      }
+      sys.push_back(s);
+    }
+  }
+  return GSM_OK;
+}
+
+void build_groups(const std::vector<SysDesc>& sys, std::vector<Group>& groups) {
+  groups.clear();
+  std::map<std::array<int, 4>, int> key2g;
+  for (int i = 0; i < (int)sys.size(); ++i) {
+    const SysDesc& s = sys[i];
+    std::array<int, 4> key{s.M[0], s.M[1], s.M[2], s.P};
+    auto it = key2g.find(key);
+    if (it == key2g.end()) {
+      Group g;
+      GroupShape& sh = g.shape;
+      for (int a = 0; a < 3; ++a) {
+        sh.M[a] = s.M[a];
+        sh.N1[a] = 2 * s.M[a] + 1;
+      }
+      sh.P = s.P;
+      sh.npencil = sh.N1[0] * sh.N1[1];
+      sh.n = 3LL * sh.npencil * sh.N1[2];
+      sh.tsize = 3LL * sh.npencil * s.P;
+      sh.nchunk = (int)((sh.n + kGsChunk - 1) / kGsChunk);
+      key2g[key] = (int)groups.size();
+      groups.push_back(g);
+      it = key2g.find(key);
+    }
+    groups[it->second].sys.push_back(i);
+  }
+  for (auto& g : groups) g.shape.S = (int)g.sys.size();
+}
+
+// Carve one group's buffers from base (base == nullptr: size only).
+size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c) {
+  const long long S = g.shape.S, n = g.shape.n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return (void*)p;
+  };
+  g.par = (SysParam*)take(S * sizeof(SysParam));
+  g.st = (SysState*)take(S * sizeof(SysState));
+  g.flags = (int*)take(S * sizeof(int));
+  g.x64 = (double2*)take(S * n * sizeof(double2));
+  g.r64 = (double2*)take(S * n * sizeof(double2));
+  g.V = take(S * (restart + 1) * n * vbytes);
+  g.T = (double2*)take(S * g.shape.tsize * sizeof(double2));
+  g.part1 = (double2*)take(S * g.shape.nchunk * (restart + 1) * sizeof(double2));
+  g.part2 = (double2*)take(S * g.shape.nchunk * (restart + 1) * sizeof(double2));
+  g.partn = (double*)take(S * g.shape.nchunk * sizeof(double));
+  g.partc = (double*)take(S * nblk_c * sizeof(double));
+  return off;
+}
+
+int nblk_c_for(const GroupShape& sh, bool dbl) {
+  const int npb = pass_c_pencils_per_block(sh.P, dbl);
+  return (sh.npencil + npb - 1) / npb;
+}
+
+size_t workspace_for(std::vector<Group>& groups, int restart, bool fp64) {
+  size_t total = 0;
+  for (auto& g : groups) {
+    // the pass C partials are written by the FP64 residual pass
+    g.shape.nblk_c = nblk_c_for(g.shape, true);
+    total += layout_group(g, nullptr, restart, fp64 ? sizeof(double2) : sizeof(float2),
+                          std::max(nblk_c_for(g.shape, true), nblk_c_for(g.shape, false)));
+  }
+  return total + 256;
+}
+
+int carve(std::vector<Group>& groups, void* ws, size_t ws_bytes, int restart, bool fp64) {
+  const size_t need = workspace_for(groups, restart, fp64);
+  if (!ws) return fail(GSM_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(GSM_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  char* p = (char*)(((uintptr_t)ws + 255) & ~uintptr_t(255));
+  for (auto& g : groups) {
+    const size_t sz = layout_group(g, p, restart, fp64 ? sizeof(double2) : sizeof(float2),
+                                   std::max(nblk_c_for(g.shape, true), nblk_c_for(g.shape, false)));
+    p += sz;
+  }
+  return GSM_OK;
+}
+
+// ------------------------------------------------------------ plan grids --
+
+int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** out) {
+  std::array<int, 4> key{M[0], M[1], M[2], P};
+  auto it = plan->grids.find(key);
+  if (it != plan->grids.end()) {
+    *out = &it->second;
+    return GSM_OK;
+  }
+  Grid g;
+  const long long P3 = (long long)P * P * P;
+  const int nb[3] = {4 * M[0] + 1, 4 * M[1] + 1, 4 * M[2] + 1};
+  const long long nbt = (long long)nb[0] * nb[1] * nb[2];
+  double2 *blk = nullptr, *t1 = nullptr, *t2 = nullptr;
+  HIP_TRY(hipMalloc(&g.g64, P3 * sizeof(double)));
+  HIP_TRY(hipMalloc(&g.g32, P3 * sizeof(float)));
+  HIP_TRY(hipMalloc(&blk, nbt * sizeof(double2)));
+  HIP_TRY(hipMalloc(&t1, std::max((long long)P * nb[1] * nb[2], P3) * sizeof(double2)));
+  HIP_TRY(hipMalloc(&t2, P3 * sizeof(double2)));
+  const int off[3] = {2 * plan->mmax[0] - 2 * M[0], 2 * plan->mmax[1] - 2 * M[1], 2 * plan->mmax[2] - 2 * M[2]};
+  HIP_TRY(launch_copy_block(plan->d_coef, blk, plan->nc, nb, off, st));
+  // x: blk[nz][ny][nbx] -> t1[nz][ny][P]
+  HIP_TRY(launch_dft_axis(blk, t1, nb[2] * nb[1], nb[0], P, 1, -2 * M[0], 0, P, +1, st));
+  // y: t1[nz][nby][P] -> t2[nz][P][P]
+  HIP_TRY(launch_dft_axis(t1, t2, nb[2], nb[1], P, P, -2 * M[1], 0, P, +1, st));
+  // z: t2[nbz][P*P] -> t1[P][P*P]
+  HIP_TRY(launch_dft_axis(t2, t1, 1, nb[2], P, P * P, -2 * M[2], 0, P, +1, st));
+  HIP_TRY(launch_extract_grid(t1, g.g64, g.g32, P3, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipFree(blk));
+  HIP_TRY(hipFree(t1));
+  HIP_TRY(hipFree(t2));
+  plan->grids[key] = g;
+  *out = &plan->grids[key];
+  return GSM_OK;
+}
+
+int ensure_flags(gsm_plan_s* plan, int n) {
+  if (plan->h_flags_cap >= n) return GSM_OK;
+  if (plan->h_flags) HIP_TRY(hipHostFree(plan->h_flags));
+  plan->h_flags = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&plan->h_flags, std::max(n, 64) * sizeof(int), hipHostMallocDefault));
+  plan->h_flags_cap = std::max(n, 64);
+  return GSM_OK;
+}
+
+// ---------------------------------------------------------------- kernels --
+
+template <typename T>
+PassArgs<T> pass_args(const Group& g, const Grid* grid) {
+  PassArgs<T> a{};
+  a.g = g.shape;
+  a.par = g.par;
+  a.st = g.st;
+  a.t = (cplx<T>*)g.T;
+  a.grid = sizeof(T) == 8 ? (const T*)grid->g64 : (const T*)grid->g32;
+  a.partial = g.partc;
+  return a;
+}
+
+template <typename T>
+KrylovArgs<T> krylov_args(const Group& g, int restart) {
+  KrylovArgs<T> k{};
+  k.g = g.shape;
+  k.par = g.par;
+  k.st = g.st;
+  k.V = (cplx<T>*)g.V;
+  k.restart = restart;
+  k.part1 = g.part1;
+  k.part2 = g.part2;
+  k.partn = g.partn;
+  k.x64 = g.x64;
+  k.r64 = g.r64;
+  k.partc = g.partc;
+  return k;
+}
+
+template <typename T>
+int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st) {
+  PassArgs<T> aa = a;
+  aa.mode = pa_mode;
+  HIP_TRY(launch_pass_a<T>(aa, st));
+  HIP_TRY(launch_pass_b<T>(a, st));
+  HIP_TRY(launch_pass_c<T>(a, st));
+  return GSM_OK;
+}
+
+// The solve loop of one group.
+template <typename T>
+int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const gsm_solver_opts* so,
+              const Grid* grid, hipStream_t st) {
+  const int S = g.shape.S;
+  const long long n = g.shape.n;
+  const int m = so->restart;
+  const bool fp64 = sizeof(T) == 8;
+  int rc = ensure_flags(plan, S);
+  if (rc) return rc;
+  HIP_TRY(launch_state_init(g.shape, g.st, g.x64, nullptr, st));
+  if (so->x0) {
+    for (int k = 0; k < S; ++k)
+      HIP_TRY(hipMemcpyAsync(g.x64 + (long long)k * n, so->x0 + 2 * sys[g.sys[k]].out_off, n * sizeof(double2),
+                             hipMemcpyDeviceToDevice, st));
+  }
+  KrylovArgs<double> k64 = krylov_args<double>(g, m);
+  KrylovArgs<T> kt = krylov_args<T>(g, m);
+  PassArgs<double> r = pass_args<double>(g, grid);
+  r.g.nblk_c = nblk_c_for(g.shape, true);
+  k64.g.nblk_c = r.g.nblk_c;
+  r.x = g.x64;
+  r.xs = n;
+  r.y = g.r64;
+  r.ys = n;
+  r.mode = PC_RESID;
+  r.gate = GATE_OUTER;
+  PassArgs<T> p = pass_args<T>(g, grid);
+  p.g.nblk_c = nblk_c_for(g.shape, fp64);
+  p.xs = (long long)(m + 1) * n;
+  p.ys = p.xs;
+  p.mode = PC_FWD;
+  p.gate = GATE_INNER;
+  cplx<T>* V = (cplx<T>*)g.V;
+  const int cap = so->max_refine + 2;
+  for (int outer = 0; outer < cap; ++outer) {
+    rc = apply_passes<double>(r, 0, st);
+    if (rc) return rc;
+    HIP_TRY(launch_resid_finalize(k64, fp64 ? 1 : 0, g.flags, st));
+    HIP_TRY(hipMemcpyAsync(plan->h_flags, g.flags, S * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bool any = false;
+    for (int s = 0; s < S; ++s) any |= plan->h_flags[s] != 0;
+    if (!any) break;
+    HIP_TRY(launch_cast_v0<T>(kt, st));
+    for (int j = 0; j < m; ++j) {
+      p.x = V + (long long)j * n;
+      p.y = V + (long long)(j + 1) * n;
+      rc = apply_passes<T>(p, j > 0 ? PA_NORMALIZE : 0, st);
+      if (rc) return rc;
+      HIP_TRY(launch_gs_dot<T>(kt, j, st));
+      HIP_TRY(launch_gs_update1<T>(kt, j, st));
+      HIP_TRY(launch_gs_update2<T>(kt, j, st));
+      HIP_TRY(launch_givens<T>(kt, j, st));
+    }
+    HIP_TRY(launch_lsq_update<T>(kt, st));
+  }
+  return GSM_OK;
+}
+
+__global__ void k_export(const SysState* st, const double2* x64, GroupShape g, SysExport* out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= g.S) return;
+  SysExport e{};
+  e.status = st[s].status;
+  e.iters = st[s].iters;
+  e.refinements = st[s].refinements;
+  e.rel = st[s].rel;
+  const long long i0 = ((long long)g.M[2] * g.N1[1] + g.M[1]) * g.N1[0] + g.M[0];
+  const long long cs = (long long)g.npencil * g.N1[2];
+  for (int c = 0; c < 3; ++c) {
+    e.e0[c] = x64[(long long)s * g.n + c * cs + i0];
+    e.w0[c] = st[s].w0[c];
+  }
+  out[s] = e;
+}
+
+int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& groups, const gsm_solver_opts* so,
+              void* ws, size_t ws_bytes, double* E_out, bool out_host, std::vector<SysExport>& exp,
+              hipStream_t st) {
+  const bool fp64 = so->precision == GSM_FP64;
+  int rc = carve(groups, ws, ws_bytes, so->restart, fp64);
+  if (rc) return rc;
+  exp.assign(sys.size(), SysExport{});
+  SysExport* d_exp = nullptr;
+  HIP_TRY(hipMalloc(&d_exp, std::max<size_t>(1, sys.size()) * sizeof(SysExport)));
+  for (auto& g : groups) {
+    Grid* grid = nullptr;
+    rc = ensure_grid(plan, g.shape.M, g.shape.P, st, &grid);
+    if (rc) break;
+    std::vector<SysParam> par;
+    for (int si : g.sys) par.push_back(sys[si].par);
+    HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    rc = fp64 ? run_group<double>(plan, g, sys, so, grid, st) : run_group<float>(plan, g, sys, so, grid, st);
+    if (rc) break;
+    for (int k = 0; k < g.shape.S; ++k) {
+      const SysDesc& s = sys[g.sys[k]];
+      HIP_TRY(hipMemcpyAsync(E_out + 2 * s.out_off, g.x64 + (long long)k * g.shape.n, s.n * sizeof(double2),
+                             out_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(k_export, dim3((g.shape.S + 63) / 64), dim3(64), 0, st, g.st, g.x64, g.shape, d_exp);
+    HIP_TRY(hipGetLastError());
+    std::vector<SysExport> ge(g.shape.S);
+    HIP_TRY(hipMemcpyAsync(ge.data(), d_exp, g.shape.S * sizeof(SysExport), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int k = 0; k < g.shape.S; ++k) exp[g.sys[k]] = ge[k];
+  }
+  hipFree(d_exp);
+  return rc;
+}
+
+void fill_info(const std::vector<SysDesc>& sys, const std::vector<SysExport>& exp, gsm_solve_info* info,
+               int* worst) {
+  for (size_t i = 0; i < sys.size(); ++i) {
+    gsm_solve_info& f = info[i];
+    f.status = exp[i].status == 0 ? GSM_OK : GSM_W_NOT_CONVERGED;
+    f.iterations = exp[i].iters;
+    f.refinements = exp[i].refinements;
+    f.fft_size = sys[i].P;
+    f.rel_residual = exp[i].rel;
+    f.eps_b = sys[i].par.eps_b;
+    if (f.status == GSM_W_NOT_CONVERGED) *worst = GSM_W_NOT_CONVERGED;
+  }
+}
+
+int set_device(const gsm_plan_s* plan) {
+  HIP_TRY(hipSetDevice(plan->device));
+  return GSM_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI ==
+
+extern "C" {
+
+int gsm_version(void) { return GSM_VERSION; }
+
+const char* gsm_strerror(int s) {
+  switch (s) {
+    case GSM_OK: return "ok";
+    case GSM_W_NOT_CONVERGED: return "not converged within the iteration caps";
+    case GSM_E_ARG: return "invalid argument";
+    case GSM_E_NONFINITE: return "non-finite input";
+    case GSM_E_NOMEM: return "out of device memory";
+    case GSM_E_DEVICE: return "HIP runtime error";
+    case GSM_E_SINGULAR: return "singular Green factor or effective-tensor system";
+    case GSM_E_WORKSPACE: return "workspace missing or too small";
+    case GSM_E_UNSUPPORTED: return "unsupported size";
+    default: return "unknown status";
+  }
+}
+
+const char* gsm_last_error(void) { return g_err.c_str(); }
+
+void gsm_solver_opts_default(gsm_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->tol = 1e-9;
+  o->inner_tol = 1e-5;
+  o->restart = 30;
+  o->max_iter = 5000;
+  o->max_refine = 200;
+  o->precision = GSM_MIXED;
+  o->method = GSM_GMRES;
+  o->flags = 0;
+  o->x0 = nullptr;
+}
+
+int gsm_fft_size(const int32_t M[3]) {
+  if (!M) return fail(GSM_E_ARG, "M is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (M[a] < 0 || M[a] > kMaxOrder) return fail(GSM_E_UNSUPPORTED, "M[%d]=%d outside [0, %d]", a, M[a], kMaxOrder);
+  return fft_size_for(M);
+}
+
+int gsm_plan_validate(const gsm_geometry* geo, const gsm_plan_opts* opts, int32_t n_inst,
+                      const gsm_instance* inst) {
+  int rc;
+  if (geo && (rc = check_geometry(geo))) return rc;
+  if (opts && (rc = check_plan_opts(opts))) return rc;
+  if (n_inst < 0) return fail(GSM_E_ARG, "n_inst < 0");
+  if (n_inst > 0) {
+    if (!inst) return fail(GSM_E_ARG, "instances are NULL");
+    double mean = 1, mn = 1, mx = 1;
+    if (geo) {
+      const long long nv = (long long)geo->nvox[0] * geo->nvox[1] * geo->nvox[2];
+      double s = 0;
+      mn = INFINITY;
+      mx = 0;
+      for (long long i = 0; i < nv; ++i) {
+        s += geo->eps[i];
+        mn = std::min(mn, geo->eps[i]);
+        mx = std::max(mx, geo->eps[i]);
+      }
+      mean = s / nv;
+    }
+    const double per[3] = {geo ? geo->period[0] : 1.0, geo ? geo->period[1] : 1.0, geo ? geo->period[2] : 1.0};
+    for (int i = 0; i < n_inst; ++i) {
+      if ((rc = check_instance(inst[i], opts ? opts->m_max : nullptr, i, true))) return rc;
+      if (inst[i].eps_b > 0 || geo) {
+        double eb;
+        if ((rc = resolve_eps_b(per, mean, mn, mx, inst[i], i, &eb))) return rc;
+      }
+    }
+  }
+  return GSM_OK;
+}
+
+int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out) {
+  int rc;
+  if (!out) return fail(GSM_E_ARG, "out is NULL");
+  if ((rc = check_geometry(geo)) || (rc = check_plan_opts(opts))) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GSM_E_DEVICE, "no HIP device");
+  if (opts->device < 0 || opts->device >= ndev) return fail(GSM_E_ARG, "device %d not present", opts->device);
+  auto* p = new gsm_plan_s();
+  p->device = opts->device;
+  for (int a = 0; a < 3; ++a) {
+    p->period[a] = geo->period[a];
+    p->vox[a] = geo->nvox[a];
+    p->mmax[a] = opts->m_max[a];
+    p->nc[a] = 4 * opts->m_max[a] + 1;
+  }
+  const long long nv = (long long)p->vox[0] * p->vox[1] * p->vox[2];
+  double s = 0, mn = INFINITY, mx = 0;
+  for (long long i = 0; i < nv; ++i) {
+    s += geo->eps[i];
+    mn = std::min(mn, geo->eps[i]);
+    mx = std::max(mx, geo->eps[i]);
+  }
+  p->eps_mean = s / nv;
+  p->eps_min = mn;
+  p->eps_max = mx;
+  auto cleanup = [&](int code) {
+    gsm_plan_destroy(p);
+    return code;
+  };
+  if ((rc = set_device(p))) return cleanup(rc);
+  double* d_eps = nullptr;
+  double2 *a = nullptr, *b = nullptr;
+  const long long ncx = p->nc[0], ncy = p->nc[1], ncz = p->nc[2];
+  const long long na = std::max(nv, (long long)p->vox[2] * ncy * ncx);
+  const long long nb = (long long)p->vox[2] * p->vox[1] * ncx;
+  hipError_t e = hipMalloc(&d_eps, nv * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&a, na * sizeof(double2));
+  if (e == hipSuccess) e = hipMalloc(&b, nb * sizeof(double2));
+  if (e == hipSuccess) e = hipMalloc(&p->d_coef, ncx * ncy * ncz * sizeof(double2));
+  if (e != hipSuccess) {
+    hipFree(d_eps);
+    hipFree(a);
+    hipFree(b);
+    return cleanup(fail(GSM_E_NOMEM, "plan allocation: %s", hipGetErrorString(e)));
+  }
+  hipStream_t st = nullptr;
+  auto run = [&]() -> int {
+    HIP_TRY(hipMemcpy(d_eps, geo->eps, nv * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(launch_real_to_complex(d_eps, a, nv, st));
+    // voxel DFT along x: a[vz][vy][vx] -> b[vz][vy][ncx], n = j - 2 m_max
+    HIP_TRY(launch_dft_axis(a, b, p->vox[2] * p->vox[1], p->vox[0], (int)ncx, 1, 0, -2 * p->mmax[0], p->vox[0], -1, st));
+    // along y: b[vz][vy][ncx] -> a[vz][ncy][ncx]
+    HIP_TRY(launch_dft_axis(b, a, p->vox[2], p->vox[1], (int)ncy, (int)ncx, 0, -2 * p->mmax[1], p->vox[1], -1, st));
+    // along z: a[vz][ncy*ncx] -> coef[ncz][ncy*ncx]
+    HIP_TRY(launch_dft_axis(a, p->d_coef, 1, p->vox[2], (int)ncz, (int)(ncy * ncx), 0, -2 * p->mmax[2], p->vox[2], -1, st));
+    HIP_TRY(launch_box_factor(p->d_coef, p->nc, p->vox, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return GSM_OK;
+  };
+  rc = run();
+  hipFree(d_eps);
+  hipFree(a);
+  hipFree(b);
+  if (rc) return cleanup(rc);
+  *out = p;
+  return GSM_OK;
+}
+
+int gsm_plan_destroy(gsm_plan_t p) {
+  if (!p) return GSM_OK;
+  hipSetDevice(p->device);
+  for (auto& kv : p->grids) {
+    hipFree(kv.second.g64);
+    hipFree(kv.second.g32);
+  }
+  hipFree(p->d_coef);
+  if (p->h_flags) hipHostFree(p->h_flags);
+  delete p;
+  return GSM_OK;
+}
+
+int gsm_plan_coefficients(gsm_plan_t p, double* c_out) {
+  if (!p || !c_out) return fail(GSM_E_ARG, "NULL argument");
+  int rc;
+  if ((rc = set_device(p))) return rc;
+  const long long n = (long long)p->nc[0] * p->nc[1] * p->nc[2];
+  HIP_TRY(hipMemcpy(c_out, p->d_coef, n * sizeof(double2), hipMemcpyDeviceToHost));
+  return GSM_OK;
+}
+
+int gsm_plan_contrast_grid(gsm_plan_t p, const int32_t M[3], int32_t P, double* g_out) {
+  if (!p || !M || !g_out) return fail(GSM_E_ARG, "NULL argument");
+  for (int a = 0; a < 3; ++a)
+    if (M[a] < 0 || M[a] > p->mmax[a]) return fail(GSM_E_ARG, "M[%d]=%d outside the plan", a, M[a]);
+  bool ok = false;
+  for (int q : kSupportedP) ok |= q == P;
+  if (!ok) return fail(GSM_E_UNSUPPORTED, "P=%d is not a supported FFT size", P);
+  for (int a = 0; a < 3; ++a)
+    if (P < 4 * M[a] + 1) return fail(GSM_E_ARG, "P=%d < 4 M + 1", P);
+  int rc;
+  if ((rc = set_device(p))) return rc;
+  Grid* g = nullptr;
+  int Mi[3] = {M[0], M[1], M[2]};
+  if ((rc = ensure_grid(p, Mi, P, nullptr, &g))) return rc;
+  HIP_TRY(hipMemcpy(g_out, g->g64, (size_t)P * P * P * sizeof(double), hipMemcpyDeviceToHost));
+  return GSM_OK;
+}
+
+int gsm_basis_eps(gsm_plan_t p, const gsm_instance* inst, double* eps_b) {
+  if (!p || !inst || !eps_b) return fail(GSM_E_ARG, "NULL argument");
+  int rc = check_instance(*inst, p->mmax, 0, false);
+  if (rc) return rc;
+  return resolve_eps_b(p->period, p->eps_mean, p->eps_min, p->eps_max, *inst, 0, eps_b);
+}
+
+int gsm_workspace_size(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const gsm_solver_opts* so,
+                       size_t* bytes) {
+  if (!p || !bytes) return fail(GSM_E_ARG, "NULL argument");
+  if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(GSM_E_ARG, "bad instance list");
+  gsm_solver_opts d;
+  if (!so) {
+    gsm_solver_opts_default(&d);
+    so = &d;
+  }
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  std::vector<SysDesc> sys;
+  // size for three drives per instance when that is larger (gsm_eff_tensor)
+  std::vector<SysDesc> sys3;
+  if ((rc = build_systems(p, n_inst, inst, so, true, sys3))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys3, groups);
+  *bytes = workspace_for(groups, so->restart, so->precision == GSM_FP64);
+  return GSM_OK;
+}
+
+int gsm_solve(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const gsm_solver_opts* so, void* ws,
+              size_t ws_bytes, double* E_out, gsm_solve_info* info, void* stream) {
+  if (!p || !inst || n_inst < 1 || !E_out || !info) return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  if ((rc = set_device(p))) return rc;
+  std::vector<SysDesc> sys;
+  if ((rc = build_systems(p, n_inst, inst, so, false, sys))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys, groups);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<SysExport> exp;
+  rc = solve_all(p, sys, groups, so, ws, ws_bytes, E_out, (so->flags & GSM_OUT_HOST) != 0, exp, st);
+  if (rc) return rc;
+  int worst = GSM_OK;
+  fill_info(sys, exp, info, &worst);
+  return worst;
+}
+
+int gsm_apply(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t precision, int32_t mode,
+              const void* x, void* y, void* ws, size_t ws_bytes, void* stream) {
+  if (!p || !inst || n_inst < 1 || !x || !y) return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  if (precision != GSM_FP64 && precision != GSM_MIXED) return fail(GSM_E_ARG, "unknown precision");
+  if (mode != GSM_APPLY_FORWARD && mode != GSM_APPLY_ADJOINT) return fail(GSM_E_ARG, "unknown mode");
+  int rc;
+  if ((rc = set_device(p))) return rc;
+  gsm_solver_opts so;
+  gsm_solver_opts_default(&so);
+  so.precision = precision;
+  std::vector<SysDesc> sys;
+  if ((rc = build_systems(p, n_inst, inst, &so, false, sys))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys, groups);
+  if ((rc = carve(groups, ws, ws_bytes, so.restart, precision == GSM_FP64))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const bool dbl = precision == GSM_FP64;
+  const size_t eb = dbl ? sizeof(double2) : sizeof(float2);
+  for (auto& g : groups) {
+    Grid* grid = nullptr;
+    if ((rc = ensure_grid(p, g.shape.M, g.shape.P, st, &grid))) return rc;
+    std::vector<SysParam> par;
+    for (int si : g.sys) par.push_back(sys[si].par);
+    HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
+    // gather inputs into the group's staging vectors (x64 slot), outputs to r64 slot
+    for (int k = 0; k < g.shape.S; ++k) {
+      const SysDesc& s = sys[g.sys[k]];
+      HIP_TRY(hipMemcpyAsync((char*)g.x64 + k * g.shape.n * eb, (const char*)x + s.out_off * eb, s.n * eb,
+                             hipMemcpyDeviceToDevice, st));
+    }
+    const int pa_mode = mode == GSM_APPLY_ADJOINT ? PA_GREEN_PRE : 0;
+    const int pc_mode = mode == GSM_APPLY_ADJOINT ? PC_ADJ : PC_FWD;
+    if (dbl) {
+      PassArgs<double> a = pass_args<double>(g, grid);
+      a.g.nblk_c = nblk_c_for(g.shape, true);
+      a.x = g.x64;
+      a.y = g.r64;
+      a.xs = a.ys = g.shape.n;
+      a.mode = pc_mode;
+      a.gate = GATE_NONE;
+      if ((rc = apply_passes<double>(a, pa_mode, st))) return rc;
+    } else {
+      PassArgs<float> a = pass_args<float>(g, grid);
+      a.g.nblk_c = nblk_c_for(g.shape, false);
+      a.x = (float2*)g.x64;
+      a.y = (float2*)g.r64;
+      a.xs = a.ys = g.shape.n;
+      a.mode = pc_mode;
+      a.gate = GATE_NONE;
+      if ((rc = apply_passes<float>(a, pa_mode, st))) return rc;
+    }
+    for (int k = 0; k < g.shape.S; ++k) {
+      const SysDesc& s = sys[g.sys[k]];
+      HIP_TRY(hipMemcpyAsync((char*)y + s.out_off * eb, (const char*)g.r64 + k * g.shape.n * eb, s.n * eb,
+                             hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return GSM_OK;
+}
+
+int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const gsm_solver_opts* so,
+                   double* eps_eff, double* E_save, void* ws, size_t ws_bytes, gsm_solve_info* info,
+                   void* stream) {
+  if (!p || !inst || n_inst < 1 || !eps_eff || !info) return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  if ((rc = set_device(p))) return rc;
+  std::vector<SysDesc> sys;
+  if ((rc = build_systems(p, n_inst, inst, so, true, sys))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys, groups);
+  hipStream_t st = (hipStream_t)stream;
+  long long total = 0;
+  for (auto& s : sys) total += s.n;
+  double* E = E_save;
+  double* tmp = nullptr;
+  if (!E) {
+    HIP_TRY(hipMalloc(&tmp, std::max<long long>(1, total) * sizeof(double2)));
+    E = tmp;
+  }
+  std::vector<SysExport> exp;
+  gsm_solver_opts so2 = *so;
+  so2.flags &= ~GSM_OUT_HOST;
+  rc = solve_all(p, sys, groups, &so2, ws, ws_bytes, E, false, exp, st);
+  if (tmp) hipFree(tmp);
+  if (rc) return rc;
+  int worst = GSM_OK;
+  fill_info(sys, exp, info, &worst);
+  using cd = std::complex<double>;
+  for (int i = 0; i < n_inst; ++i) {
+    cd E0[3][3], D0[3][3];
+    for (int d = 0; d < 3; ++d) {
+      const SysExport& e = exp[3 * i + d];
+      const double eb = sys[3 * i + d].par.eps_b;
+      for (int c = 0; c < 3; ++c) {
+        E0[c][d] = cd(e.e0[c].x, e.e0[c].y);
+        D0[c][d] = eb * (cd(e.e0[c].x, e.e0[c].y) + cd(e.w0[c].x, e.w0[c].y));
+      }
+    }
+    // inverse of E0 by cofactors
+    const cd det = E0[0][0] * (E0[1][1] * E0[2][2] - E0[1][2] * E0[2][1]) -
+                   E0[0][1] * (E0[1][0] * E0[2][2] - E0[1][2] * E0[2][0]) +
+                   E0[0][2] * (E0[1][0] * E0[2][1] - E0[1][1] * E0[2][0]);
+    double scale = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) scale = std::max(scale, std::abs(E0[r][c]));
+    if (!(std::abs(det) > 1e-14 * scale * scale * scale))
+      return fail(GSM_E_SINGULAR, "instance %d: zeroth-order field matrix E0 is singular", i);
+    cd inv[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+        inv[r][c] = (E0[r1][c1] * E0[r2][c2] - E0[r1][c2] * E0[r2][c1]) / det;
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        cd v = 0;
+        for (int k = 0; k < 3; ++k) v += D0[r][k] * inv[k][c];
+        eps_eff[(9 * i + 3 * r + c) * 2] = v.real();
+        eps_eff[(9 * i + 3 * r + c) * 2 + 1] = v.imag();
+      }
+  }
+  return worst;
+}
+
+int gsm_solve_adjoint(gsm_plan_t, int32_t, const gsm_instance*, const gsm_solver_opts*, const double*, double*,
+                      void*, size_t, gsm_solve_info*, void*) {
+  return fail(GSM_E_UNSUPPORTED, "gsm_solve_adjoint: not built yet");
+}
+
+int gsm_eff_tensor_vjp(gsm_plan_t, int32_t, const gsm_instance*, const gsm_solver_opts*, const double*,
+                       const double*, const double*, double*, void*, size_t, gsm_solve_info*, void*) {
+  return fail(GSM_E_UNSUPPORTED, "gsm_eff_tensor_vjp: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+#!/usr/bin/env python3
+"""Build libgsm.so for gfx950 in-tree: generate the FFT codelets, compile each
+translation unit with hipcc in parallel and link the shared library next to
+the Python package.  Usage: python build.py [--jobs N]"""
+import argparse
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.dirname(HERE)
+BUILD = os.path.join(PKG, "_build")
+UNITS = ["tu_passes_f32.hip", "tu_passes_f64.hip", "tu_krylov.hip", "tu_plan.hip", "api.hip"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
+         # packed FP32 instructions stay out of the generated code
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
+
+
+def run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise SystemExit(f"build failed: {cmd[-1]}")
+    return r
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
+    args = ap.parse_args()
+    os.makedirs(BUILD, exist_ok=True)
+    run([sys.executable, os.path.join(HERE, "gen_fft.py"), os.path.join(HERE, "fft_codelets.h")])
+
+    def compile_unit(u):
+        obj = os.path.join(BUILD, u.replace(".hip", ".o"))
+        run([HIPCC] + FLAGS + ["-c", os.path.join(HERE, u), "-o", obj])
+        return obj
+
+    with ThreadPoolExecutor(args.jobs) as ex:
+        objs = list(ex.map(compile_unit, UNITS))
+    out = os.path.join(PKG, "libgsm.so")
+    tmp = out + ".tmp"
+    run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, out)
+    print(out)
+
+
+if __name__ == "__main__":
+    main()

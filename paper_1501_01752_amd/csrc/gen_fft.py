@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Generate straight-line, pruned FFT codelets for the GSM pass kernels.
+
+Each codelet computes a length-N DFT restricted to a set of non-zero input
+residues and a set of wanted output residues,
+
+    out[j] = sum_{k in inputs} in[k] * exp(sign * 2 pi i * k * j / N),
+
+by mixed-radix decimation in time (radix 4, then 2, 3, 5), built as a
+data-flow graph of real additions and constant multiplications.  Zero inputs
+are propagated, multiplications by 0, +-1 and +-i disappear, and only the
+operations that feed a wanted output are emitted.  The result is a
+``__device__ __forceinline__`` template over the real type (float or double)
+that works on register arrays, so every twiddle is a literal constant.
+
+Usage: gen_fft.py OUT_HEADER
+"""
+import math
+import sys
+from fractions import Fraction
+
+# --------------------------------------------------------------- DAG --------
+
+
+class Graph:
+    def __init__(self):
+        self.nodes = []          # (op, args...)
+        self.memo = {}
+
+    def node(self, *key):
+        if key in self.memo:
+            return self.memo[key]
+        self.nodes.append(key)
+        idx = len(self.nodes) - 1
+        self.memo[key] = idx
+        return idx
+
+
+ZERO = None   # a real value that is exactly zero
+
+
+def neg(x):
+    if x is ZERO:
+        return ZERO
+    return (x[0], not x[1])
+
+
+class Builder:
+    """Real-valued expressions as (node, negated) references."""
+
+    def __init__(self):
+        self.g = Graph()
+
+    def inp(self, slot, part):
+        return (self.g.node('in', slot, part), False)
+
+    def add(self, x, y):
+        if x is ZERO:
+            return y
+        if y is ZERO:
+            return x
+        if x[1] and y[1]:
+            return neg(self.add(neg(x), neg(y)))
+        if x[1]:
+            return self._sub(y, neg(x))
+        if y[1]:
+            return self._sub(x, neg(y))
+        a, b = sorted((x[0], y[0]))
+        return (self.g.node('add', a, b), False)
+
+    def _sub(self, x, y):          # x, y positive references
+        if x[0] == y[0]:
+            return ZERO
+        return (self.g.node('sub', x[0], y[0]), False)
+
+    def sub(self, x, y):
+        return self.add(x, neg(y))
+
+    def mul(self, x, c):
+        if x is ZERO or c == 0.0:
+            return ZERO
+        if c == 1.0:
+            return x
+        if c == -1.0:
+            return neg(x)
+        if c < 0:
+            return neg(self.mul(x, -c))
+        return (self.g.node('mul', x[0], repr(float(c))), x[1])
+
+
+def _cs(num, den):
+    """exp(2 pi i num/den) with exact values at multiples of pi/4."""
+    f = Fraction(num, den) % 1
+    exact = {Fraction(0): (1.0, 0.0), Fraction(1, 4): (0.0, 1.0), Fraction(1, 2): (-1.0, 0.0),
+             Fraction(3, 4): (0.0, -1.0)}
+    if f in exact:
+        return exact[f]
+    r = math.sqrt(0.5)
+    eighth = {Fraction(1, 8): (r, r), Fraction(3, 8): (-r, r), Fraction(5, 8): (-r, -r),
+              Fraction(7, 8): (r, -r)}
+    if f in eighth:
+        return eighth[f]
+    ang = 2.0 * math.pi * float(f)
+    return (math.cos(ang), math.sin(ang))
+
+
+class C:
+    """Complex value as a pair of real references."""
+
+    def __init__(self, re, im):
+        self.re, self.im = re, im
+
+    def is_zero(self):
+        return self.re is ZERO and self.im is ZERO
+
+
+def cadd(b, x, y):
+    return C(b.add(x.re, y.re), b.add(x.im, y.im))
+
+
+def csub(b, x, y):
+    return C(b.sub(x.re, y.re), b.sub(x.im, y.im))
+
+
+def ctw(b, x, num, den):
+    """x * exp(2 pi i num / den)."""
+    if x.is_zero():
+        return x
+    c, s = _cs(num, den)
+    if s == 0.0:
+        return C(b.mul(x.re, c), b.mul(x.im, c))
+    if c == 0.0:     # +-i
+        return C(b.mul(x.im, -s), b.mul(x.re, s))
+    if abs(abs(c) - abs(s)) < 1e-300:
+        # (c + i s) with |c| = |s| = r: two adds and two multiplications
+        r = abs(c)
+        re = b.sub(b.mul(x.re, c / r), b.mul(x.im, s / r))
+        im = b.add(b.mul(x.re, s / r), b.mul(x.im, c / r))
+        return C(b.mul(re, r), b.mul(im, r))
+    re = b.sub(b.mul(x.re, c), b.mul(x.im, s))
+    im = b.add(b.mul(x.re, s), b.mul(x.im, c))
+    return C(re, im)
+
+
+def _radix(n):
+    for r in (4, 2, 3, 5):
+        if n % r == 0:
+            return r
+    raise ValueError(f'size {n} is not 2,3,5-smooth')
+
+
+def dft(b, xs, n, sign):
+    """Decimation in time; xs: list of n complex values (possibly zero)."""
+    if n == 1:
+        return list(xs)
+    if all(x.is_zero() for x in xs):
+        return [C(ZERO, ZERO) for _ in range(n)]
+    r = _radix(n)
+    m = n // r
+    subs = [dft(b, xs[j::r], m, sign) for j in range(r)]
+    out = [None] * n
+    for k in range(m):
+        t = [ctw(b, subs[j][k], sign * j * k, n) for j in range(r)]
+        for q in range(r):
+            acc = C(ZERO, ZERO)
+            for j in range(r):
+                acc = cadd(b, acc, ctw(b, t[j], sign * j * q, r))
+            out[k + q * m] = acc
+    return out
+
+
+# ------------------------------------------------------------- emitter ------
+
+def build_codelet(n, in_slots, out_slots, sign):
+    b = Builder()
+    xs = [C(ZERO, ZERO) for _ in range(n)]
+    for i, s in enumerate(in_slots):
+        xs[s] = C(b.inp(i, 0), b.inp(i, 1))
+    ys = dft(b, xs, n, sign)
+    outs = [ys[s] for s in out_slots]
+    return b, outs
+
+
+def emit(name, n, in_slots, out_slots, sign):
+    b, outs = build_codelet(n, in_slots, out_slots, sign)
+    nodes = b.g.nodes
+    used = set()
+    stack = []
+    for o in outs:
+        for r in (o.re, o.im):
+            if r is not ZERO:
+                stack.append(r[0])
+    while stack:
+        i = stack.pop()
+        if i in used:
+            continue
+        used.add(i)
+        op = nodes[i]
+        if op[0] in ('add', 'sub'):
+            stack += [op[1], op[2]]
+        elif op[0] == 'mul':
+            stack.append(op[1])
+    lines = []
+    nin, nout = len(in_slots), len(out_slots)
+    lines.append(f'// {name}: N={n}, {nin} non-zero inputs, {nout} outputs, sign {sign:+d}')
+    lines.append('template <typename T>')
+    lines.append(f'__device__ __forceinline__ void {name}(const T (&ir)[{nin}], const T (&ii)[{nin}],'
+                 f' T (&orr)[{nout}], T (&oi)[{nout}]) {{')
+    nflop = 0
+    for i in sorted(used):
+        op = nodes[i]
+        if op[0] == 'in':
+            src = 'ir' if op[2] == 0 else 'ii'
+            lines.append(f'  const T v{i} = {src}[{op[1]}];')
+        elif op[0] == 'add':
+            lines.append(f'  const T v{i} = v{op[1]} + v{op[2]};')
+            nflop += 1
+        elif op[0] == 'sub':
+            lines.append(f'  const T v{i} = v{op[1]} - v{op[2]};')
+            nflop += 1
+        elif op[0] == 'mul':
+            lines.append(f'  const T v{i} = v{op[1]} * T({op[2]});')
+            nflop += 1
+
+    def ref(r):
+        if r is ZERO:
+            return 'T(0)'
+        return ('-' if r[1] else '') + f'v{r[0]}'
+    for j, o in enumerate(outs):
+        lines.append(f'  orr[{j}] = {ref(o.re)};')
+        lines.append(f'  oi[{j}] = {ref(o.im)};')
+    lines.append('}')
+    lines.insert(1, f'// real operations: {nflop}')
+    return '\n'.join(lines) + '\n', nflop
+
+
+def expand_slots(n, k):
+    return [x % n for x in range(-k, k + 1)], list(range(n))
+
+
+def crop_slots(n, k):
+    return list(range(n)), [x % n for x in range(-k, k + 1)]
+
+
+def codelet_specs():
+    """(name, N, in_slots, out_slots, sign) for every codelet the kernels use.
+
+    expand (e): inputs at residues of -K..K, all N outputs, sign +1 (field to
+    real space); crop (c): all N inputs, outputs at -K..K, sign -1; full (f).
+    """
+    specs = []
+    pairs = set()
+    # transform size P with K = (P-1)//4 (R = 1) and the split halves (R = 2):
+    for p in (4, 8, 16, 32, 64, 128):
+        k = (p - 1) // 4
+        pairs.add((p, k))
+        if p >= 8:
+            pairs.add((p // 2, k))
+    for n, k in sorted(pairs):
+        if 2 * k + 1 > n:
+            continue
+        i, o = expand_slots(n, k)
+        specs.append((f'fft_e{n}_{k}', n, i, o, +1))
+        i, o = crop_slots(n, k)
+        specs.append((f'fft_c{n}_{k}', n, i, o, -1))
+    for n in (32,):
+        specs.append((f'fft_fp{n}', n, list(range(n)), list(range(n)), +1))
+        specs.append((f'fft_fm{n}', n, list(range(n)), list(range(n)), -1))
+    return specs
+
+
+def twiddle_table(n):
+    vals = [_cs(j, n) for j in range(n)]
+    body = ',\n'.join(f'  {{{c!r}, {s!r}}}' for c, s in vals)
+    return f'__device__ constexpr double kTw{n}[{n}][2] = {{\n{body}\n}};\n'
+
+
+def dispatch(name, n, nin, nout, kind, param):
+    return (f'template <> struct Codelet{kind}<{n}, {param}> {{\n'
+            f'  template <typename T> __device__ static __forceinline__ void run('
+            f'const T (&ir)[{nin}], const T (&ii)[{nin}], T (&orr)[{nout}], T (&oi)[{nout}]) {{\n'
+            f'    {name}<T>(ir, ii, orr, oi);\n  }}\n}};\n')
+
+
+def main(path):
+    out = ['// Generated by gen_fft.py: straight-line pruned DFT codelets. Do not edit.',
+           '#pragma once', '#include <hip/hip_runtime.h>', '',
+           '// CodeletE<N, K>: inputs at residues of -K..K (in that order), all N outputs,',
+           '//   out[j] = sum_k in[k] exp(+2 pi i k j / N).',
+           '// CodeletC<N, K>: all N inputs, outputs at residues of -K..K,',
+           '//   out[k] = sum_j in[j] exp(-2 pi i k j / N).',
+           '// CodeletF<N, S>: full transform with sign S (+1 or -1).',
+           'template <int N, int K> struct CodeletE;',
+           'template <int N, int K> struct CodeletC;',
+           'template <int N, int S> struct CodeletF;', '']
+    total = 0
+    for name, n, i, o, s in codelet_specs():
+        src, nf = emit(name, n, i, o, s)
+        out.append(src)
+        total += nf
+        if name.startswith('fft_e'):
+            out.append(dispatch(name, n, len(i), len(o), 'E', (len(i) - 1) // 2))
+        elif name.startswith('fft_c'):
+            out.append(dispatch(name, n, len(i), len(o), 'C', (len(o) - 1) // 2))
+        else:
+            out.append(dispatch(name, n, len(i), len(o), 'F', s))
+    for n in (8, 16, 32, 64, 128):
+        out.append(twiddle_table(n))
+    with open(path, 'w') as f:
+        f.write('\n'.join(out))
+
+
+if __name__ == '__main__':
+    main(sys.argv[1])

@@ -1,0 +1,141 @@
+// Internal declarations of libgsm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gsm {
+
+constexpr int kMaxRestart = 64;   // largest Krylov dimension per cycle
+constexpr int kMaxOrder = 31;     // largest M_a (P = 128)
+constexpr int kGsThreads = 256;   // block size of the Gram-Schmidt kernels
+constexpr int kGsPerThread = 4;   // vector elements per thread in those kernels
+constexpr int kGsChunk = kGsThreads * kGsPerThread;
+
+template <typename T> struct cplx_t;
+template <> struct cplx_t<float> { using type = float2; };
+template <> struct cplx_t<double> { using type = double2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+// Per-system constants (device memory, written once per solve).
+struct SysParam {
+  double q0[3];      // k_inc / k0
+  double b[3];       // lambda / Lambda_a  (= K_a / k0)
+  double eps_b;      // basis permittivity
+  double inv_eps_b;
+  double a[6];       // drive amplitude (re, im) x 3  (incident field at m = 0)
+  double bnorm;      // ||a||_2 = ||b||_2 of the right-hand side
+  double tol;        // outer relative residual target
+  double inner_tol;  // relative reduction asked of one Krylov cycle
+  int max_iter;
+  int max_refine;
+  int pad[2];
+};
+
+// Per-system solver state (device memory).
+struct SysState {
+  int active;        // outer refinement still running
+  int inner_active;  // current Krylov cycle still running
+  int j;             // Arnoldi steps completed in the current cycle
+  int iters;         // total Krylov iterations
+  int refinements;   // FP64 residual evaluations
+  int status;        // 0 running/converged, 1 not converged
+  int pad[2];
+  double rho;        // ||r|| of the last FP64 residual
+  double rel;        // rho / bnorm
+  double vscale;     // factor applied to V[j] by the next pass A (normalisation)
+  double inner_target;
+  double xscale;     // factor applied to the Krylov correction (rho)
+  double pad2;
+  double2 w0[3];     // zeroth order of the contrast convolution (last FP64 pass)
+  double2 g[kMaxRestart + 1];
+  double2 H[(kMaxRestart + 1) * kMaxRestart];  // column j at H[j * (kMaxRestart+1) + i]
+  double cs[kMaxRestart];
+  double2 sn[kMaxRestart];
+  double2 y[kMaxRestart];
+  double2 h1[kMaxRestart + 1];
+  double2 h2[kMaxRestart + 1];
+};
+
+// Shape of a group: systems sharing (M, P).
+struct GroupShape {
+  int S;            // systems in the group
+  int M[3];
+  int N1[3];
+  int P;
+  int npencil;      // N1x * N1y
+  long long n;      // 3 * N1x * N1y * N1z complex values per system
+  long long tsize;  // 3 * npencil * P complex values per system (intermediate)
+  int nchunk;       // ceil(n / kGsChunk)
+  int nblk_c;       // pass C blocks per system
+};
+
+// pass A modes
+enum { PA_NORMALIZE = 1, PA_GREEN_PRE = 2 };
+// pass C modes
+enum { PC_FWD = 0, PC_RESID = 1, PC_ADJ = 2, PC_ADJ_RESID = 3, PC_CONV = 4 };
+// gating of blocks by state
+enum { GATE_NONE = 0, GATE_INNER = 1, GATE_OUTER = 2 };
+
+template <typename T>
+struct PassArgs {
+  GroupShape g;
+  const SysParam* par;
+  SysState* st;
+  cplx<T>* x;           // pass A input / pass C "x"
+  cplx<T>* t;           // intermediate (per system stride g.tsize)
+  cplx<T>* y;           // pass C output
+  const cplx<T>* rhs;   // PC_ADJ_RESID right-hand side, else unused
+  long long xs, ys, rs; // per-system strides (complex values) of x, y, rhs
+  const T* grid;        // band-limited permittivity, P^3 real [z][y][x]
+  double* partial;      // pass C residual partials [S][nblk_c]
+  int mode;
+  int gate;
+};
+
+// ---- launchers (passes.hip) ----
+template <typename T> hipError_t launch_pass_a(const PassArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_pass_b(const PassArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_pass_c(const PassArgs<T>& a, hipStream_t s);
+int pass_c_pencils_per_block(int P, bool dbl);
+bool fft_size_supported(int P);
+
+// ---- Krylov / refinement kernels (krylov.hip) ----
+template <typename T>
+struct KrylovArgs {
+  GroupShape g;
+  const SysParam* par;
+  SysState* st;
+  cplx<T>* V;          // basis [S][restart+1][n]
+  int restart;
+  double2* part1;      // [S][nchunk][restart+1]
+  double2* part2;      // [S][nchunk][restart+1]
+  double* partn;       // [S][nchunk]
+  double2* x64;        // [S][n] FP64 iterate
+  double2* r64;        // [S][n] FP64 residual
+  double* partc;       // [S][nblk_c] pass C residual partials
+};
+template <typename T> hipError_t launch_gs_dot(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_gs_update1(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_gs_update2(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_givens(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_lsq_update(const KrylovArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_cast_v0(const KrylovArgs<T>& a, hipStream_t s);
+hipError_t launch_resid_finalize(const KrylovArgs<double>& a, int fp64_inner, int* flags, hipStream_t s);
+hipError_t launch_state_init(const GroupShape& g, SysState* st, double2* x64, const double2* x0,
+                             hipStream_t s);
+
+// ---- plan kernels (plan.hip) ----
+// out[o][j][i] = sum_{k<nin} in[o][k][i] * exp(sign 2 pi i ((k+koff)(j+joff) mod Q) / Q)
+hipError_t launch_dft_axis(const double2* in, double2* out, int nouter, int nin, int nout,
+                           int ninner, int koff, int joff, int Q, int sign, hipStream_t s);
+hipError_t launch_real_to_complex(const double* in, double2* out, long long n, hipStream_t s);
+hipError_t launch_box_factor(double2* c, const int nc[3], const int vox[3], hipStream_t s);
+hipError_t launch_extract_grid(const double2* in, double* g64, float* g32, long long n,
+                               hipStream_t s);
+hipError_t launch_copy_block(const double2* src, double2* dst, const int src_n[3],
+                             const int dst_n[3], const int off[3], hipStream_t s);
+
+}  // namespace gsm

@@ -1,0 +1,279 @@
+"""ctypes binding of libgsm (include/gsm.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts NumPy/torch
+arguments to the C structures, allocates the device workspace as a torch
+uint8 tensor and passes torch's current HIP stream.  It raises if the
+library has not been built (``python paper_1501_01752_amd/csrc/build.py``).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsm.so")
+
+GSM_OK, GSM_W_NOT_CONVERGED = 0, 1
+GSM_E_ARG, GSM_E_NONFINITE, GSM_E_NOMEM, GSM_E_DEVICE = -1, -2, -3, -4
+GSM_E_SINGULAR, GSM_E_WORKSPACE, GSM_E_UNSUPPORTED = -5, -6, -7
+GSM_MIXED, GSM_FP64 = 0, 1
+GSM_GMRES = 0
+GSM_OUT_HOST = 1
+GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT = 0, 1
+
+
+class Geometry(C.Structure):
+    _fields_ = [("period", C.c_double * 3), ("nvox", C.c_int32 * 3), ("eps", C.POINTER(C.c_double))]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("m_max", C.c_int32 * 3), ("device", C.c_int32), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("wavelength", C.c_double), ("k_inc", C.c_double * 3), ("M", C.c_int32 * 3),
+                ("n_drive", C.c_int32), ("pol", (C.c_double * 6) * 3), ("eps_b", C.c_double)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int32),
+                ("max_iter", C.c_int32), ("max_refine", C.c_int32), ("precision", C.c_int32),
+                ("method", C.c_int32), ("flags", C.c_int32), ("x0", C.c_void_p)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("refinements", C.c_int32),
+                ("fft_size", C.c_int32), ("rel_residual", C.c_double), ("eps_b", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GsmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libgsm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+_SIGS = {
+    "gsm_version": (C.c_int, []),
+    "gsm_strerror": (C.c_char_p, [C.c_int]),
+    "gsm_last_error": (C.c_char_p, []),
+    "gsm_solver_opts_default": (None, [C.POINTER(SolverOpts)]),
+    "gsm_fft_size": (C.c_int, [C.POINTER(C.c_int32)]),
+    "gsm_plan_validate": (C.c_int, [C.POINTER(Geometry), C.POINTER(PlanOpts), C.c_int32,
+                                    C.POINTER(Instance)]),
+    "gsm_basis_eps": (C.c_int, [C.c_void_p, C.POINTER(Instance), C.POINTER(C.c_double)]),
+    "gsm_plan": (C.c_int, [C.POINTER(Geometry), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
+    "gsm_plan_destroy": (C.c_int, [C.c_void_p]),
+    "gsm_plan_coefficients": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsm_plan_contrast_grid": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_void_p]),
+    "gsm_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance),
+                                     C.POINTER(SolverOpts), C.POINTER(C.c_size_t)]),
+    "gsm_solve": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.POINTER(SolverOpts),
+                            C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(SolveInfo), C.c_void_p]),
+    "gsm_apply": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.c_int32, C.c_int32,
+                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gsm_eff_tensor": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.POINTER(SolverOpts),
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                 C.POINTER(SolveInfo), C.c_void_p]),
+    "gsm_solve_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.POINTER(SolverOpts),
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.POINTER(SolveInfo), C.c_void_p]),
+    "gsm_eff_tensor_vjp": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance),
+                                     C.POINTER(SolverOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(SolveInfo),
+                                     C.c_void_p]),
+}
+
+
+def lib():
+    """Load libgsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "python paper_1501_01752_amd/csrc/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status, allow_warn=True):
+    if status < 0 or (status > 0 and not allow_warn):
+        raise GsmError(status, lib().gsm_last_error().decode())
+    return status
+
+
+def default_opts(**kw):
+    o = SolverOpts()
+    lib().gsm_solver_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def fft_size(M):
+    return lib().gsm_fft_size((C.c_int32 * 3)(*M))
+
+
+def make_instance(wavelength, k_inc, M, drives=((1.0, 0.0, 0.0),), eps_b=0.0):
+    """One (omega, k) point; drives are up to three complex 3-vectors."""
+    inst = Instance()
+    inst.wavelength = float(wavelength)
+    for a in range(3):
+        inst.k_inc[a] = float(k_inc[a])
+        inst.M[a] = int(M[a])
+    drives = list(drives)
+    inst.n_drive = len(drives)
+    for d, vec in enumerate(drives):
+        for c in range(3):
+            z = complex(vec[c])
+            inst.pol[d][2 * c] = z.real
+            inst.pol[d][2 * c + 1] = z.imag
+    inst.eps_b = float(eps_b)
+    return inst
+
+
+def instances_array(insts):
+    arr = (Instance * len(insts))()
+    for i, x in enumerate(insts):
+        arr[i] = x
+    return arr
+
+
+def system_sizes(insts, three=False):
+    out = []
+    for x in insts:
+        n = 3 * (2 * x.M[0] + 1) * (2 * x.M[1] + 1) * (2 * x.M[2] + 1)
+        out += [n] * (3 if three else x.n_drive)
+    return out
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+class Plan:
+    """Owning handle of a gsm_plan_t built from a voxel body."""
+
+    def __init__(self, eps, period=(1.0, 1.0, 1.0), m_max=(15, 15, 15), device=0):
+        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+        vz, vy, vx = self.eps.shape
+        g = Geometry()
+        for a in range(3):
+            g.period[a] = float(period[a])
+        g.nvox[0], g.nvox[1], g.nvox[2] = vx, vy, vz
+        g.eps = self.eps.ctypes.data_as(C.POINTER(C.c_double))
+        o = PlanOpts()
+        for a in range(3):
+            o.m_max[a] = int(m_max[a])
+        o.device = device
+        h = C.c_void_p()
+        _check(lib().gsm_plan(C.byref(g), C.byref(o), C.byref(h)), allow_warn=False)
+        self.handle = h
+        self.m_max = tuple(int(m) for m in m_max)
+        self.period = tuple(float(p) for p in period)
+        self.device = device
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().gsm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def coefficients(self):
+        n = [4 * m + 1 for m in self.m_max]
+        out = np.zeros((n[2], n[1], n[0]), dtype=np.complex128)
+        _check(lib().gsm_plan_coefficients(self.handle, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def contrast_grid(self, M, P):
+        out = np.zeros((P, P, P), dtype=np.float64)
+        _check(lib().gsm_plan_contrast_grid(self.handle, (C.c_int32 * 3)(*M), P,
+                                            out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def basis_eps(self, inst):
+        v = C.c_double()
+        _check(lib().gsm_basis_eps(self.handle, C.byref(inst), C.byref(v)))
+        return v.value
+
+    def workspace(self, insts, opts):
+        import torch
+        arr = instances_array(insts)
+        nb = C.c_size_t()
+        _check(lib().gsm_workspace_size(self.handle, len(insts), arr, C.byref(opts), C.byref(nb)))
+        need = int(nb.value)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def solve(self, insts, opts=None, x0=None, stream=None):
+        """Solve every (instance, drive); returns (E as a flat complex128 torch
+        tensor on the device, list of per-system info dicts, status)."""
+        import torch
+        opts = opts or default_opts()
+        arr = instances_array(insts)
+        n = sum(system_sizes(insts))
+        E = torch.empty(n, dtype=torch.complex128, device=f"cuda:{self.device}")
+        info = (SolveInfo * len(system_sizes(insts)))()
+        if x0 is not None:
+            x0 = x0.contiguous()
+            opts.x0 = x0.data_ptr()
+        ws = self.workspace(insts, opts)
+        st = lib().gsm_solve(self.handle, len(insts), arr, C.byref(opts), C.c_void_p(ws.data_ptr()),
+                             ws.numel(), C.c_void_p(E.data_ptr()), info, _stream(stream))
+        _check(st)
+        return E, [i.as_dict() for i in info], st
+
+    def apply(self, insts, x, precision=GSM_FP64, mode=GSM_APPLY_FORWARD, stream=None):
+        """y = A x (or A^H x) for every (instance, drive) vector in x."""
+        import torch
+        opts = default_opts(precision=precision)
+        arr = instances_array(insts)
+        x = x.contiguous()
+        want = torch.complex128 if precision == GSM_FP64 else torch.complex64
+        if x.dtype != want:
+            raise TypeError(f"x must be {want}")
+        y = torch.empty_like(x)
+        ws = self.workspace(insts, opts)
+        _check(lib().gsm_apply(self.handle, len(insts), arr, precision, mode, C.c_void_p(x.data_ptr()),
+                               C.c_void_p(y.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
+                               _stream(stream)))
+        return y
+
+    def eff_tensor(self, insts, opts=None, save_fields=False, stream=None):
+        """eps_eff = D0 E0^-1 per instance (numpy [n, 3, 3] complex128)."""
+        import torch
+        opts = opts or default_opts()
+        arr = instances_array(insts)
+        out = np.zeros((len(insts), 3, 3), dtype=np.complex128)
+        info = (SolveInfo * (3 * len(insts)))()
+        E = None
+        if save_fields:
+            E = torch.empty(sum(system_sizes(insts, three=True)), dtype=torch.complex128,
+                            device=f"cuda:{self.device}")
+        ws = self.workspace(insts, opts)
+        st = lib().gsm_eff_tensor(self.handle, len(insts), arr, C.byref(opts),
+                                  out.ctypes.data_as(C.c_void_p),
+                                  C.c_void_p(E.data_ptr() if E is not None else 0),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), info, _stream(stream))
+        _check(st)
+        return out, E, [i.as_dict() for i in info], st

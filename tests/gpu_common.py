@@ -1,0 +1,53 @@
+"""Shared helpers of the GPU parity tests: build the same seeded case for the
+HIP library and for the CPU oracle."""
+import sys
+
+import numpy as np
+
+from oracle import gsm as O
+from paper_1501_01752_amd import inputs
+
+
+def say(msg):
+    """Name the case before each GPU step (flushed, so a fault still shows it)."""
+    sys.stdout.write(f"[gpu-case] {msg}\n")
+    sys.stdout.flush()
+
+
+def torch_dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def k_vector(wavelength, k_hat, n_inc=1.0):
+    k0 = 2 * np.pi / wavelength
+    k = np.asarray(k_hat, dtype=np.float64)
+    k = k / np.linalg.norm(k) if np.linalg.norm(k) > 0 else k
+    return n_inc * k0 * k
+
+
+def oracle_case(eps, period, wavelength, k_inc, M):
+    c = O.box_image(eps, tuple(2 * m for m in M))
+    q = O.harmonic_q(k_inc, wavelength, period, M)
+    return c, q
+
+
+def asym_body():
+    eps = inputs.ellipsoid((6, 5, 7), (1.0, 0.9, 1.1), (0.3, 0.25, 0.35), 5.0)
+    eps[1, 2, 3] = 8.0
+    eps[4, 0, 1] = 2.5
+    return eps
+
+
+def seeded_field(shape, seed, dtype=np.complex128):
+    rng = np.random.default_rng(seed)
+    return (rng.normal(size=shape) + 1j * rng.normal(size=shape)).astype(dtype)
+
+
+def to_torch(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch_dev())
+
+
+def rel_err(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))

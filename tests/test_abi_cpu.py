@@ -1,0 +1,124 @@
+"""The C-ABI library loads and exports every symbol include/gsm.h declares;
+host-side validation and error codes (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1501_01752_amd import gsm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gsm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = gsm.lib()
+    names = _declared()
+    assert "gsm_solve" in names and "gsm_plan" in names and "gsm_eff_tensor" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.gsm_version() == 100
+
+
+def test_binding_covers_declared_symbols():
+    assert set(_declared()) <= set(gsm._SIGS)
+
+
+def test_strerror_and_defaults():
+    L = gsm.lib()
+    assert L.gsm_strerror(gsm.GSM_E_SINGULAR)
+    o = gsm.default_opts()
+    assert o.tol == 1e-9 and o.inner_tol == 1e-5 and o.restart == 30
+    assert o.precision == gsm.GSM_MIXED
+
+
+@pytest.mark.parametrize("M,P", [((0, 0, 0), 4), ((1, 1, 1), 8), ((3, 3, 3), 16), ((3, 1, 0), 16),
+                                 ((7, 2, 2), 32), ((15, 15, 15), 64), ((16, 6, 6), 128),
+                                 ((31, 31, 31), 128)])
+def test_fft_size(M, P):
+    assert gsm.fft_size(M) == P
+    assert P >= 4 * max(M) + 1
+
+
+def test_fft_size_unsupported():
+    assert gsm.fft_size((32, 0, 0)) == gsm.GSM_E_UNSUPPORTED
+
+
+def _geom(eps, period=(1.0, 1.0, 1.0)):
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    g = gsm.Geometry()
+    for a in range(3):
+        g.period[a] = period[a]
+    g.nvox[0], g.nvox[1], g.nvox[2] = eps.shape[2], eps.shape[1], eps.shape[0]
+    g.eps = eps.ctypes.data_as(C.POINTER(C.c_double))
+    return g, eps
+
+
+def _popts(m=(3, 3, 3)):
+    o = gsm.PlanOpts()
+    for a in range(3):
+        o.m_max[a] = m[a]
+    return o
+
+
+def _validate(geo=None, po=None, insts=()):
+    arr = gsm.instances_array(list(insts)) if insts else None
+    return gsm.lib().gsm_plan_validate(C.byref(geo) if geo else None, C.byref(po) if po else None,
+                                       len(insts), arr)
+
+
+def test_validate_ok():
+    g, keep = _geom(np.full((4, 4, 4), 2.0))
+    inst = gsm.make_instance(1 / 0.3, (0, 0, 2 * np.pi * 0.3), (3, 3, 3))
+    assert _validate(g, _popts(), [inst]) == gsm.GSM_OK
+
+
+def test_validate_nan_voxel():
+    e = np.full((4, 4, 4), 2.0)
+    e[1, 2, 3] = np.nan
+    g, keep = _geom(e)
+    assert _validate(g) == gsm.GSM_E_NONFINITE
+    assert b"eps" in gsm.lib().gsm_last_error()
+
+
+def test_validate_bad_sizes():
+    g, keep = _geom(np.full((4, 4, 4), 2.0), period=(1.0, -1.0, 1.0))
+    assert _validate(g) == gsm.GSM_E_ARG
+    assert _validate(None, _popts((40, 0, 0))) == gsm.GSM_E_UNSUPPORTED
+    g, keep = _geom(np.full((4, 4, 4), -2.0))
+    assert _validate(g) == gsm.GSM_E_ARG
+
+
+def test_validate_instance_errors():
+    g, keep = _geom(np.full((4, 4, 4), 2.0))
+    bad = gsm.make_instance(-1.0, (0, 0, 1), (3, 3, 3))
+    assert _validate(g, _popts(), [bad]) == gsm.GSM_E_ARG
+    big = gsm.make_instance(1.0, (0, 0, 1), (5, 3, 3))
+    assert _validate(g, _popts(), [big]) == gsm.GSM_E_ARG
+    nod = gsm.make_instance(1.0, (0, 0, 1), (3, 3, 3), drives=[])
+    assert _validate(g, _popts(), [nod]) == gsm.GSM_E_ARG
+
+
+def test_validate_singular_explicit_eps_b():
+    # |q_0|^2 = 1 for |k_inc| = k0: eps_b = 1 puts the m = 0 harmonic on the light cone
+    g, keep = _geom(np.full((4, 4, 4), 2.0))
+    lam = 1 / 0.3
+    inst = gsm.make_instance(lam, (0, 0, 2 * np.pi / lam), (3, 3, 3), eps_b=1.0)
+    assert _validate(g, _popts(), [inst]) == gsm.GSM_E_SINGULAR
+    inst.eps_b = 1.2
+    assert _validate(g, _popts(), [inst]) == gsm.GSM_OK
+
+
+def test_validate_auto_eps_b_dodges_light_cone():
+    # uniform vacuum: <eps> = 1 = |q_0|^2, the policy must pick another eps_b
+    g, keep = _geom(np.full((4, 4, 4), 1.0))
+    lam = 1 / 0.3
+    inst = gsm.make_instance(lam, (0, 0, 2 * np.pi / lam), (3, 3, 3))
+    assert _validate(g, _popts(), [inst]) == gsm.GSM_OK

@@ -1,0 +1,299 @@
+"""HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Plan coefficients and contrast grids, the operator of Eq.(4) (forward and
+adjoint, complex128 and complex64), solves (FP64 and mixed precision), the
+effective tensor.  Sizes span several FFT grids (P = 4 ... 128), anisotropic
+order counts, oblique incidence and ragged pencil counts."""
+import numpy as np
+import pytest
+
+from gpu_common import asym_body, k_vector, oracle_case, rel_err, say, seeded_field, to_torch
+from oracle import gsm as O
+from paper_1501_01752_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def G():
+    from paper_1501_01752_amd import gsm
+    return gsm
+
+
+# ----------------------------------------------------------------- plan ----
+
+PLAN_CASES = {
+    "sphere16_m3": (lambda: inputs.sphere(16, 0.3, 4.0), (1, 1, 1), (3, 3, 3)),
+    "asym_m231": (asym_body, (1.0, 0.9, 1.1), (2, 3, 1)),
+    "stack64_m15z": (lambda: inputs.layered_stack(64, 0.4, 2.25, 9.0), (1, 1, 1), (0, 0, 15)),
+    "random32_m12": (lambda: inputs.smooth_random_field(32, seed=4), (1, 1, 1), (12, 12, 12)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PLAN_CASES))
+def test_plan_coefficients(name):
+    mk, period, mmax = PLAN_CASES[name]
+    eps = mk()
+    say(f"plan coefficients {name}")
+    plan = G().Plan(eps, period, mmax)
+    c_gpu = plan.coefficients()
+    c_or = O.box_image(eps, tuple(2 * m for m in mmax))
+    assert np.abs(c_gpu - c_or).max() <= 1e-13 * np.abs(c_or).max()
+
+
+@pytest.mark.parametrize("name,M,P", [("sphere16_m3", (3, 3, 3), 16), ("asym_m231", (2, 3, 1), 16),
+                                      ("asym_m231", (1, 2, 1), 32), ("random32_m12", (12, 12, 12), 64)])
+def test_contrast_grid(name, M, P):
+    mk, period, mmax = PLAN_CASES[name]
+    eps = mk()
+    say(f"contrast grid {name} M={M} P={P}")
+    plan = G().Plan(eps, period, mmax)
+    g = plan.contrast_grid(M, P)
+    c = O.box_image(eps, tuple(2 * m for m in M))
+    grid = np.zeros((P, P, P), complex)
+    for iz, nz in enumerate(range(-2 * M[2], 2 * M[2] + 1)):
+        for iy, ny in enumerate(range(-2 * M[1], 2 * M[1] + 1)):
+            nx = np.arange(-2 * M[0], 2 * M[0] + 1)
+            grid[nz % P, ny % P, nx % P] = c[iz, iy, :]
+    ref = np.fft.ifftn(grid) * P ** 3
+    assert np.abs(ref.imag).max() < 1e-12
+    assert np.abs(g - ref.real).max() <= 1e-12 * np.abs(ref).max()
+
+
+# -------------------------------------------------------------- operator ---
+
+OP_CASES = {
+    # name: (eps maker, period, wavelength, k_hat, n_inc, M)
+    "m0": (lambda: inputs.sphere(8, 0.3, 4.0), (1, 1, 1), 1 / 0.3, (0, 0, 1), 1.0, (0, 0, 0)),
+    "m1": (asym_body, (1.0, 0.9, 1.1), 1 / 0.35, (0.3, 0.4, 0.866), 1.0, (1, 1, 1)),
+    "sphere_m3": (lambda: inputs.sphere(16, 0.3, 4.0), (1, 1, 1), 1 / 0.3, (0, 0, 1), 1.0, (3, 3, 3)),
+    "asym_m213": (asym_body, (1.0, 0.9, 1.1), 1 / 0.35, (0.3, 0.4, 0.866), 1.0, (2, 1, 3)),
+    "asym_m7": (asym_body, (1.0, 0.9, 1.1), 1 / 0.25, (-0.5, 0.2, 0.5), 0.8, (7, 5, 6)),
+    "random_m12": (lambda: inputs.smooth_random_field(32, seed=4), (1, 1, 1), 1 / 0.3, (0, 0, 1), 1.0,
+                   (12, 12, 12)),
+    "sphere_m15": (lambda: inputs.sphere(64, 0.3, 4.0), (1, 1, 1), 1 / 0.3, (0, 0, 1), 1.0, (15, 15, 15)),
+    "aniso_p128": (asym_body, (1.0, 0.9, 1.1), 1 / 0.4, (0.1, 0.2, 0.97), 1.0, (6, 5, 17)),
+}
+
+
+def _op_setup(name, ndrive=2):
+    mk, period, lam, khat, n_inc, M = OP_CASES[name]
+    eps = mk()
+    k = k_vector(lam, khat, n_inc)
+    gsm = G()
+    drives = [(1, 0, 0), (0, 1, 0.5j)][:ndrive]
+    inst = gsm.make_instance(lam, k, M, drives)
+    plan = gsm.Plan(eps, period, M)
+    eb = plan.basis_eps(inst)
+    inst.eps_b = eb
+    c, q = oracle_case(eps, period, lam, k, M)
+    return plan, inst, c, q, eb, M
+
+
+@pytest.mark.parametrize("name", sorted(OP_CASES))
+def test_apply_fp64(name):
+    plan, inst, c, q, eb, M = _op_setup(name)
+    gsm = G()
+    P = gsm.fft_size(M)
+    shape = (3, 2 * M[2] + 1, 2 * M[1] + 1, 2 * M[0] + 1)
+    x = seeded_field((2,) + shape, seed=11)
+    say(f"apply fp64 {name} M={M} P={P}")
+    y = plan.apply([inst], to_torch(x.ravel()), precision=gsm.GSM_FP64).cpu().numpy().reshape((2,) + shape)
+    for d in range(2):
+        ref = O.apply_operator_fft(c, M, q, eb, x[d], (P, P, P))
+        assert rel_err(y[d], ref) <= 1e-13, name
+    if 3 * np.prod(shape[1:]) <= 3000:
+        A = O.assemble_dense(c, M, q, eb)
+        assert rel_err(y[0].ravel(), A @ x[0].ravel()) <= 1e-13
+
+
+@pytest.mark.parametrize("name", sorted(OP_CASES))
+def test_apply_fp32(name):
+    plan, inst, c, q, eb, M = _op_setup(name)
+    gsm = G()
+    P = gsm.fft_size(M)
+    shape = (3, 2 * M[2] + 1, 2 * M[1] + 1, 2 * M[0] + 1)
+    x = seeded_field((2,) + shape, seed=12, dtype=np.complex64)
+    say(f"apply fp32 {name} M={M} P={P}")
+    y = plan.apply([inst], to_torch(x.ravel()), precision=gsm.GSM_MIXED).cpu().numpy().reshape((2,) + shape)
+    for d in range(2):
+        ref = O.apply_operator_fft(c, M, q, eb, x[d].astype(np.complex128), (P, P, P))
+        assert rel_err(y[d], ref) <= 3e-6, name
+
+
+@pytest.mark.parametrize("name", ["m1", "asym_m213", "sphere_m3", "aniso_p128"])
+def test_apply_adjoint(name):
+    plan, inst, c, q, eb, M = _op_setup(name, ndrive=1)
+    gsm = G()
+    shape = (3, 2 * M[2] + 1, 2 * M[1] + 1, 2 * M[0] + 1)
+    x = seeded_field(shape, seed=13)
+    v = seeded_field(shape, seed=14)
+    say(f"apply adjoint {name}")
+    y = plan.apply([inst], to_torch(x.ravel()), precision=gsm.GSM_FP64,
+                   mode=gsm.GSM_APPLY_ADJOINT).cpu().numpy()
+    Av = O.apply_operator_fft(c, M, q, eb, v, tuple([gsm.fft_size(M)] * 3)).ravel()
+    # <A^H x, v> = <x, A v>
+    lhs = np.vdot(y, v.ravel())
+    rhs = np.vdot(x.ravel(), Av)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(Av)
+    if 3 * np.prod(shape[1:]) <= 3000:
+        A = O.assemble_dense(c, M, q, eb)
+        assert rel_err(y, A.conj().T @ x.ravel()) <= 1e-13
+
+
+# ----------------------------------------------------------------- solve ---
+
+def _solve_case(eps, period, lam, k, M, drives, eps_b=None, **opt):
+    gsm = G()
+    inst = gsm.make_instance(lam, k, M, drives)
+    plan = gsm.Plan(eps, period, M)
+    inst.eps_b = plan.basis_eps(inst) if eps_b is None else eps_b
+    opts = gsm.default_opts(**opt)
+    E, info, st = plan.solve([inst], opts)
+    return plan, inst, E.cpu().numpy(), info, st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_sphere_m3_vs_dense_lu(precision):
+    w = inputs.sphere_lattice_small()
+    gsm = G()
+    k = k_vector(w["wavelength"], w["k_hat"])
+    prec = gsm.GSM_FP64 if precision == "fp64" else gsm.GSM_MIXED
+    say(f"solve sphere M=3 {precision}")
+    plan, inst, E, info, st = _solve_case(w["eps"], w["period"], w["wavelength"], k, w["M"],
+                                          [(1, 0, 0), (0, 0.3, 1j)], tol=1e-12, precision=prec)
+    assert st == gsm.GSM_OK and all(i["rel_residual"] <= 1e-12 for i in info)
+    c, q = oracle_case(w["eps"], w["period"], w["wavelength"], k, w["M"])
+    ref = O.solve_dense(c, w["M"], q, inst.eps_b, [np.array([1, 0, 0]), np.array([0, 0.3, 1j])])
+    assert rel_err(E, ref.ravel()) <= 1e-10
+
+
+def test_solve_oblique_aniso_mixed():
+    eps = asym_body()
+    period, lam, M = (1.0, 0.9, 1.1), 1 / 0.35, (2, 3, 1)
+    k = k_vector(lam, (0.3, 0.4, 0.866))
+    gsm = G()
+    say("solve asym oblique mixed")
+    plan, inst, E, info, st = _solve_case(eps, period, lam, k, M, [(0.2, 1.0, -0.4j)], tol=1e-11)
+    c, q = oracle_case(eps, period, lam, k, M)
+    ref = O.solve_dense(c, M, q, inst.eps_b, [np.array([0.2, 1.0, -0.4j])])
+    assert st == gsm.GSM_OK
+    assert rel_err(E, ref.ravel()) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_trivial_contrast_is_incident_field(precision):
+    """Uniform eps = eps_b: the operator is exactly the identity (the contrast
+    grid is exactly zero), and the solve returns E_inc (one Krylov step from a
+    zero start, more only to clean up rounding)."""
+    gsm = G()
+    lam = 1 / 0.3
+    k = k_vector(lam, (0, 0, 1))
+    a = np.array([0.3, -0.5, 0.8])
+    prec = gsm.GSM_FP64 if precision == "fp64" else gsm.GSM_MIXED
+    say(f"solve uniform eps = eps_b {precision}")
+    plan, inst, E, info, st = _solve_case(np.full((8, 8, 8), 2.0), (1, 1, 1), lam, k, (3, 3, 3),
+                                          [tuple(a)], eps_b=2.0, precision=prec, tol=1e-13)
+    ref = O.incident_rhs((3, 3, 3), a)
+    assert st == gsm.GSM_OK and info[0]["iterations"] <= 3
+    assert np.abs(E - ref).max() <= 1e-13 * np.abs(a).max()
+    x = seeded_field(ref.shape, seed=5)
+    y = plan.apply([inst], to_torch(x), precision=gsm.GSM_FP64).cpu().numpy()
+    assert np.array_equal(y, x)
+
+
+def test_not_converged_status():
+    gsm = G()
+    w = inputs.sphere_lattice_small()
+    k = k_vector(w["wavelength"], w["k_hat"])
+    say("solve capped at one iteration")
+    plan, inst, E, info, st = _solve_case(w["eps"], w["period"], w["wavelength"], k, w["M"], [(1, 0, 0)],
+                                          tol=1e-14, max_iter=1, max_refine=2)
+    assert st == gsm.GSM_W_NOT_CONVERGED and info[0]["status"] == gsm.GSM_W_NOT_CONVERGED
+    assert info[0]["iterations"] == 1 and np.isfinite(E).all()
+
+
+def test_batch_equals_single():
+    gsm = G()
+    eps = asym_body()
+    period = (1.0, 0.9, 1.1)
+    plan = gsm.Plan(eps, period, (3, 3, 3))
+    insts = []
+    for i, (lam, kh, M) in enumerate([(1 / 0.3, (0, 0, 1), (3, 3, 3)), (1 / 0.35, (0.3, 0.4, 0.866), (2, 3, 1)),
+                                       (1 / 0.3, (1, 0, 0), (3, 3, 3)), (1 / 0.2, (0.6, 0, 0.8), (1, 1, 2))]):
+        inst = gsm.make_instance(lam, k_vector(lam, kh), M, [(1, 0, 0), (0, 1, 0)][: 1 + i % 2])
+        inst.eps_b = plan.basis_eps(inst)
+        insts.append(inst)
+    opts = gsm.default_opts(tol=1e-11)
+    say("batched solve of 4 uneven instances")
+    E, info, st = plan.solve(insts, opts)
+    E = E.cpu().numpy()
+    off = 0
+    for inst in insts:
+        say(f"single solve M={tuple(inst.M)}")
+        Es, _, _ = plan.solve([inst], gsm.default_opts(tol=1e-11))
+        n = Es.numel()
+        assert rel_err(E[off:off + n], Es.cpu().numpy()) <= 1e-9
+        off += n
+
+
+# -------------------------------------------------------------- eff tensor --
+
+def test_eff_tensor_sphere_m3():
+    w = inputs.sphere_lattice_small()
+    gsm = G()
+    k = k_vector(w["wavelength"], w["k_hat"])
+    inst = gsm.make_instance(w["wavelength"], k, w["M"])
+    plan = gsm.Plan(w["eps"], w["period"], w["M"])
+    say("eff tensor sphere M=3")
+    ee, _, info, st = plan.eff_tensor([inst], gsm.default_opts(tol=1e-12))
+    c, q = oracle_case(w["eps"], w["period"], w["wavelength"], k, w["M"])
+    ref = O.eps_eff_schur(c, w["M"], q)
+    assert st == gsm.GSM_OK
+    assert np.abs(ee[0] - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_cfg2_sphere_m15_vs_fft_gmres_oracle():
+    """31^3 harmonics, 64^3 grid, complex64 Krylov + FP64 refinement, x and y
+    drives, against the FFT-GMRES oracle at residual 1e-12."""
+    w = inputs.sphere_lattice_m15()
+    gsm = G()
+    k = k_vector(w["wavelength"], w["k_hat"])
+    say("cfg2 sphere M=15 mixed")
+    plan, inst, E, info, st = _solve_case(w["eps"], w["period"], w["wavelength"], k, w["M"], w["drives"],
+                                          tol=1e-11)
+    assert st == gsm.GSM_OK
+    c, q = oracle_case(w["eps"], w["period"], w["wavelength"], k, w["M"])
+    n = E.size // 2
+    for d, a in enumerate(w["drives"]):
+        ref, _ = O.solve_fft_gmres(c, w["M"], q, inst.eps_b, np.array(a, complex), (64, 64, 64), rtol=1e-12)
+        assert rel_err(E[d * n:(d + 1) * n], ref.ravel()) <= 1e-9
+
+
+def test_cfg2_stack_m15_vs_1d_reduction():
+    w = inputs.layered_stack_m15()
+    gsm = G()
+    k = k_vector(w["wavelength"], w["k_hat"])
+    say("cfg2 stack M=15 mixed")
+    plan, inst, E, info, st = _solve_case(w["eps"], w["period"], w["wavelength"], k, w["M"], w["drives"],
+                                          tol=1e-11)
+    assert st == gsm.GSM_OK
+    M = w["M"]
+    shape = (3, 31, 31, 31)
+    c1 = O.box_image(w["eps"], (0, 0, 30))[:, 0, 0]
+    n = E.size // 2
+    for d, a in enumerate(w["drives"]):
+        Ed = E[d * n:(d + 1) * n].reshape(shape)
+        ref = O.solve_stack_1d(c1, 15, k / (2 * np.pi / w["wavelength"]), w["wavelength"], inst.eps_b,
+                               np.array(a, complex))
+        axis = Ed[:, :, M[1], M[0]]
+        assert rel_err(axis, ref) <= 1e-9
+        off = Ed.copy()
+        off[:, :, M[1], M[0]] = 0
+        assert np.abs(off).max() <= 1e-12 * np.abs(ref).max()
