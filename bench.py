@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Benchmark: GSM solves/sec to a 1e-9 relative residual at 31^3 orders.
+
+Workload (one step): the two bodies at M = 15 (31^3 harmonics, 64^3 FFT
+grid) -- the cubic sphere lattice (Lambda = 0.3 lambda, r = 0.3 Lambda,
+eps 4 in vacuum, 64^3 voxels) and the layered stack (fill 0.4, eps 2.25 / 9)
+-- each driven by two orthogonal transverse polarisations along normal
+incidence (z) plus D seeded incidence directions (default D = 31), all
+directions of a body in one batched call; complex64 GMRES(30) inside FP64
+iterative refinement to a relative FP64 residual of 1e-9.  That is
+2 x 2 x (D + 1) = 128 solves per step, and each batched matrix-vector
+product moves more than 1 GB, well beyond the 256 MB Infinity Cache.  The
+literal 4-solve case (D = 0: x and y drives at normal incidence only) is
+timed as well and reported as "as_configured".
+
+Prints one JSON line: value = solves/s over the timed steps, the roofline of
+the dominant kernel class (algorithmic bytes over the hipEvent-measured
+duration of its launches in the timed region), the plain FP64 GPU solve of
+the same workload, and the CPU oracle (FFT + SciPy GMRES, FP64) timed on a
+bounded sample.
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--directions", type=int, default=31,
+                    help="seeded incidence directions per body besides normal incidence (batched)")
+    ap.add_argument("--config-steps", type=int, default=5, help="steps of the 4-solve case")
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    return ap.parse_args()
+
+
+def build_workload(gsm, inputs, directions):
+    bodies = [inputs.sphere_lattice_m15(), inputs.layered_stack_m15()]
+    work = []
+    for w in bodies:
+        lam, M = w["wavelength"], w["M"]
+        k0 = 2 * np.pi / lam
+        plan = gsm.Plan(w["eps"], w["period"], M)
+        insts = []
+        dirs = [np.array([0.0, 0.0, 1.0])]
+        if directions:
+            dirs += list(inputs.random_directions(directions, seed=7))
+        for khat in dirs:
+            a1 = inputs.transverse_drive(khat)
+            a2 = np.cross(khat, a1)
+            if np.allclose(khat, [0, 0, 1]):
+                a1, a2 = np.array([1.0, 0, 0]), np.array([0, 1.0, 0])
+            inst = gsm.make_instance(lam, k0 * khat, M, [tuple(a1), tuple(a2)])
+            inst.eps_b = plan.basis_eps(inst)
+            insts.append(inst)
+        work.append((plan, insts))
+    return work
+
+
+STATS = {"iterations": 0, "refinements": 0, "reorth": 0, "solves": 0}
+
+
+def run_step(gsm, work, opts):
+    nsolve = 0
+    worst = 0.0
+    for plan, insts in work:
+        E, info, st = plan.solve(insts, opts)
+        if st != gsm.GSM_OK:
+            raise RuntimeError(f"solve status {st}: {info}")
+        nsolve += len(info)
+        worst = max(worst, max(i["rel_residual"] for i in info))
+        for i in info:
+            for k in ("iterations", "refinements", "reorth"):
+                STATS[k] += i[k]
+        STATS["solves"] += len(info)
+    return nsolve, worst
+
+
+def cpu_baseline(inputs):
+    """The oracle's FFT + GMRES route (FP64) on one solve of the sphere lattice
+    at M = 15, x drive, to the same 1e-9 residual."""
+    from oracle import gsm as O
+    w = inputs.sphere_lattice_m15()
+    lam, M = w["wavelength"], w["M"]
+    k = 2 * np.pi / lam * np.array([0.0, 0.0, 1.0])
+    c = O.box_image(w["eps"], tuple(2 * m for m in M))
+    q = O.harmonic_q(k, lam, w["period"], M)
+    eb = float(np.mean(w["eps"]))
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    E, it = O.solve_fft_gmres(c, M, q, eb, np.array([1.0, 0, 0], complex), (64, 64, 64), rtol=TOL)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    return {"value": 1.0 / wall, "unit": "solves/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"1 solve (sphere lattice, M=15, x drive, FP64 numpy FFT + scipy GMRES(30) "
+                      f"to 1e-9), {it} iterations, {wall:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(instances shard across GPUs with no communication, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_1501_01752_amd import gsm, inputs
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device"}))
+        sys.exit(1)
+    work = build_workload(gsm, inputs, args.directions)
+    opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30)
+    for _ in range(args.warmup):
+        run_step(gsm, work, opts)
+    torch.cuda.synchronize()
+
+    for k in STATS:
+        STATS[k] = 0
+    gsm.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total = 0
+    worst = 0.0
+    for _ in range(args.steps):
+        n, w = run_step(gsm, work, opts)
+        total += n
+        worst = max(worst, w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = gsm.profile_end()
+    krylov = {k: round(STATS[k] / max(1, STATS["solves"]), 2) for k in ("iterations", "refinements", "reorth")}
+    dt = t1 - t0
+    value = total / dt
+
+    # dominant kernel class by time
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "avg_launch_us": round(dom["ms"] * 1e3 / max(1, dom["launches"]), 2)}
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+
+    # plain FP64 GPU solve of the same workload
+    opts64 = gsm.default_opts(tol=TOL, precision=gsm.GSM_FP64, restart=30)
+    run_step(gsm, work, opts64)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n64 = 0
+    for _ in range(args.fp64_steps):
+        n, _ = run_step(gsm, work, opts64)
+        n64 += n
+    torch.cuda.synchronize()
+    fp64_value = n64 / (time.perf_counter() - t2)
+
+    # the literal 4-solve case: x, y drives at normal incidence, both bodies
+    small = build_workload(gsm, inputs, 0)
+    run_step(gsm, small, opts)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ns = 0
+    for _ in range(args.config_steps):
+        n, _ = run_step(gsm, small, opts)
+        ns += n
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    as_configured = {"value": round(ns / (t4 - t3), 3), "unit": "solves/s", "solves_per_step": ns // args.config_steps,
+                     "ms_per_step": round((t4 - t3) / args.config_steps * 1e3, 3)}
+
+    cpu = None if args.no_cpu else cpu_baseline(inputs)
+    per_step = total // args.steps
+    line = {
+        "metric": "GSM solves/sec to 1e-9 rel. residual at 31^3 orders; matvec HBM GB/s vs peak",
+        "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": "31^3 orders (M=15), 64^3 FFT grid: sphere lattice (r=0.3 Lambda, eps 4, "
+                               "64^3 voxels) + layered stack (f=0.4, eps 2.25/9), Lambda=0.3 lambda, "
+                               f"2 transverse drives x (normal incidence + {args.directions} seeded directions) "
+                               "per body, batched; complex64 GMRES(30) + FP64 refinement to 1e-9",
+                   "solves_per_step": per_step, "max_rel_residual": worst,
+                   "per_solve_mean": krylov},
+        "roofline": roofline,
+        "fp64_gpu_solve": {"value": round(fp64_value, 3), "unit": "solves/s"},
+        "as_configured": as_configured,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

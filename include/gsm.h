@@ -122,6 +122,8 @@ typedef struct gsm_solve_info {
   int32_t iterations;  /* Krylov iterations (matrix-vector products in the Krylov precision) */
   int32_t refinements; /* FP64 residual evaluations */
   int32_t fft_size;    /* P, the FFT grid per axis */
+  int32_t reorth;      /* Arnoldi steps that needed a second Gram-Schmidt pass */
+  int32_t reserved;
   double rel_residual; /* final ||b - A x||_2 / ||b||_2 evaluated in FP64 */
   double eps_b;        /* basis permittivity used */
 } gsm_solve_info;
@@ -229,6 +231,26 @@ int gsm_eff_tensor_vjp(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst
                        const gsm_solver_opts* opts, const double* E_save,
                        const double* eps_eff, const double* gbar, double* grad_vox, void* ws,
                        size_t ws_bytes, gsm_solve_info* info, void* stream);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Per-kernel-class statistics of the launches made between
+ * gsm_profile_begin and gsm_profile_end on any stream: launch count, summed
+ * duration from a hipEvent pair recorded around each launch on its stream,
+ * and summed algorithmic bytes (what each launch must read and write by the
+ * definition of its step, counted only for the systems that work in it). */
+typedef struct gsm_kernel_stat {
+  char name[40];    /* e.g. "pass_b_c64", "gs_update1_c64" */
+  int64_t launches;
+  double ms;
+  double bytes;
+} gsm_kernel_stat;
+
+/* Start collecting (clears earlier records).  Not thread-safe. */
+int gsm_profile_begin(void);
+/* Stop, synchronise the device, write up to `max` entries to out and the
+ * number of classes seen to *n_out. */
+int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out);
 
 #ifdef __cplusplus
 }

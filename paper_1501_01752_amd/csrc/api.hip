@@ -71,7 +71,9 @@ struct gsm_plan_s {
   double2* d_coef = nullptr;
   std::map<std::array<int, 4>, Grid> grids;
   int* h_flags = nullptr;  // pinned
+  int* h_inner = nullptr;  // pinned, written by the Givens kernel
   int h_flags_cap = 0;
+  hipEvent_t step_ev[gsm::kMaxRestart] = {};
 };
 
 namespace {
@@ -142,6 +144,29 @@ int check_solver_opts(const gsm_solver_opts* s) {
 
 // -------------------------------------------------- basis permittivity ----
 
+// min over the truncated harmonic set of | |q_m|^2 - eb | (one linear scan)
+double margin_scan(const gsm_instance& in, const double* period, double eb) {
+  const double k0 = 2.0 * M_PI / in.wavelength;
+  double q0[3], b[3];
+  for (int a = 0; a < 3; ++a) {
+    q0[a] = in.k_inc[a] / k0;
+    b[a] = in.wavelength / period[a];
+  }
+  double m = INFINITY;
+  for (int mz = -in.M[2]; mz <= in.M[2]; ++mz) {
+    const double qz = q0[2] + mz * b[2];
+    for (int my = -in.M[1]; my <= in.M[1]; ++my) {
+      const double qy = q0[1] + my * b[1];
+      const double r = qy * qy + qz * qz - eb;
+      for (int mx = -in.M[0]; mx <= in.M[0]; ++mx) {
+        const double qx = q0[0] + mx * b[0];
+        m = std::min(m, std::fabs(qx * qx + r));
+      }
+    }
+  }
+  return m;
+}
+
 // sorted |q_m|^2 over the truncated harmonic set
 std::vector<double> shell_values(const gsm_instance& in, const double* period) {
   const double k0 = 2.0 * M_PI / in.wavelength;
@@ -174,17 +199,17 @@ constexpr double kSingularRel = 1e-3;
 
 int resolve_eps_b(const double* period, double eps_mean, double eps_min, double eps_max, const gsm_instance& in,
                   int idx, double* out) {
-  const std::vector<double> sh = shell_values(in, period);
   if (in.eps_b > 0) {
-    if (margin_of(sh, in.eps_b) < kSingularRel * in.eps_b)
+    if (margin_scan(in, period, in.eps_b) < kSingularRel * in.eps_b)
       return fail(GSM_E_SINGULAR, "instance %d: |k_m|^2 = k_b^2 within 1e-3 for eps_b=%g", idx, in.eps_b);
     *out = in.eps_b;
     return GSM_OK;
   }
-  if (margin_of(sh, eps_mean) >= kSingularRel * eps_mean) {
+  if (margin_scan(in, period, eps_mean) >= kSingularRel * eps_mean) {
     *out = eps_mean;
     return GSM_OK;
   }
+  const std::vector<double> sh = shell_values(in, period);
   const double lo = 0.5 * eps_min, hi = 2.0 * eps_max;
   double best = -1, best_eb = eps_mean;
   const int n = 4001;
@@ -221,16 +246,16 @@ struct Group {
   int* flags = nullptr;
   double2* x64 = nullptr;
   double2* r64 = nullptr;
+  double2* rhs64 = nullptr;  // general right-hand sides (adjoint solve)
   void* V = nullptr;
   double2* T = nullptr;
   double2* part1 = nullptr;
-  double2* part2 = nullptr;
   double* partn = nullptr;
   double* partc = nullptr;
 };
 
 struct SysExport {
-  int status, iters, refinements, pad;
+  int status, iters, refinements, reorth;
   double rel;
   double2 e0[3];
   double2 w0[3];
@@ -332,13 +357,13 @@ size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c
   };
   g.par = (SysParam*)take(S * sizeof(SysParam));
   g.st = (SysState*)take(S * sizeof(SysState));
-  g.flags = (int*)take(S * sizeof(int));
+  g.flags = (int*)take(2 * S * sizeof(int));  // [active flags | steps of the last cycle]
   g.x64 = (double2*)take(S * n * sizeof(double2));
   g.r64 = (double2*)take(S * n * sizeof(double2));
+  g.rhs64 = (double2*)take(S * n * sizeof(double2));
   g.V = take(S * (restart + 1) * n * vbytes);
   g.T = (double2*)take(S * g.shape.tsize * sizeof(double2));
-  g.part1 = (double2*)take(S * g.shape.nchunk * (restart + 1) * sizeof(double2));
-  g.part2 = (double2*)take(S * g.shape.nchunk * (restart + 1) * sizeof(double2));
+  g.part1 = (double2*)take(S * g.shape.nchunk * (restart + 2) * sizeof(double2));
   g.partn = (double*)take(S * g.shape.nchunk * sizeof(double));
   g.partc = (double*)take(S * nblk_c * sizeof(double));
   return off;
@@ -411,11 +436,16 @@ int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** 
 }
 
 int ensure_flags(gsm_plan_s* plan, int n) {
+  if (!plan->step_ev[0])
+    for (int j = 0; j < kMaxRestart; ++j) HIP_TRY(hipEventCreateWithFlags(&plan->step_ev[j], hipEventDisableTiming));
   if (plan->h_flags_cap >= n) return GSM_OK;
   if (plan->h_flags) HIP_TRY(hipHostFree(plan->h_flags));
-  plan->h_flags = nullptr;
-  HIP_TRY(hipHostMalloc((void**)&plan->h_flags, std::max(n, 64) * sizeof(int), hipHostMallocDefault));
-  plan->h_flags_cap = std::max(n, 64);
+  if (plan->h_inner) HIP_TRY(hipHostFree(plan->h_inner));
+  plan->h_flags = plan->h_inner = nullptr;
+  const int cap = std::max(n, 64);
+  HIP_TRY(hipHostMalloc((void**)&plan->h_flags, cap * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&plan->h_inner, cap * sizeof(int), hipHostMallocDefault));
+  plan->h_flags_cap = cap;
   return GSM_OK;
 }
 
@@ -442,7 +472,6 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
   k.V = (cplx<T>*)g.V;
   k.restart = restart;
   k.part1 = g.part1;
-  k.part2 = g.part2;
   k.partn = g.partn;
   k.x64 = g.x64;
   k.r64 = g.r64;
@@ -450,26 +479,119 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
   return k;
 }
 
+// ------------------------------------------------------------- profiler --
+// Optional per-launch timing: a hipEvent pair around each launch on the
+// launching stream, and the launch's algorithmic bytes (what the step must
+// read and write by its definition, counted for the systems that do work in
+// that launch).  Systems that finish a Krylov cycle early are only known at
+// the next host synchronisation, so step launches are attributed then.
+
+enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_DOT2, K_CGS_UPD2, K_LSQ, K_CAST, K_FINAL, K_NBASE };
+const char* kClassNames[K_NBASE] = {"pass_a", "pass_b", "pass_c", "cgs_dot", "cgs_update",
+                                    "cgs_dot_2nd", "cgs_update_2nd", "lsq_update", "cast_v0", "resid_finalize"};
+
+struct ProfRec {
+  int cls;        // base class * 2 + (complex128 ? 1 : 0)
+  hipEvent_t a, b;
+  double bytes;   // resolved algorithmic bytes
+  int step;       // Arnoldi step (>= 0) to resolve later, -1 resolved, -2 lsq
+  double unit;    // bytes per working system (step records)
+  int group;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  int group_tag = 0;
+} g_prof;
+
+hipEvent_t prof_event() {
+  if (g_prof.used == g_prof.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+  }
+  return g_prof.pool[g_prof.used++];
+}
+
+template <class F>
+hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f) {
+  if (!g_prof.on) return f();
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag};
+  if (r.a) hipEventRecord(r.a, st);
+  const hipError_t e = f();
+  if (r.b) hipEventRecord(r.b, st);
+  if (r.a && r.b) g_prof.recs.push_back(r);
+  return e;
+}
+
+// Resolve the step records of the cycle that just ended: jdone[s] Arnoldi
+// steps were done by system s.
+void prof_resolve(const int* jdone, int S, long long n, size_t vb) {
+  if (!g_prof.on) return;
+  for (auto& r : g_prof.recs) {
+    if (r.group != g_prof.group_tag || r.step == -1) continue;
+    double tot = 0;
+    if (r.step == -2) {
+      for (int s = 0; s < S; ++s)
+        if (jdone[s] > 0) tot += (double)jdone[s] * n * vb + 2.0 * n * sizeof(double2);
+    } else {
+      int cnt = 0;
+      for (int s = 0; s < S; ++s) cnt += jdone[s] > r.step;
+      tot = cnt * r.unit;
+    }
+    r.bytes = tot;
+    r.step = -1;
+  }
+}
+
+// Algorithmic bytes of the three passes per system (C = 3 components):
+//   pass A: read x (C N1^3 b_c), write the intermediate (C N1x N1y P b_c)
+//   pass B: read + write the intermediate, read the contrast grid (P^3 b_r)
+//   pass C: read the intermediate, read x, write y (2 C N1^3 b_c)
+struct PassBytes {
+  double a, b, c;
+};
+PassBytes pass_bytes(const GroupShape& g, size_t bc) {
+  const double vec = (double)g.n * bc, mid = (double)g.tsize * bc;
+  const double grid = (double)g.P * g.P * g.P * (bc / 2);
+  return {vec + mid, 2 * mid + grid, mid + 2 * vec};
+}
+
 template <typename T>
-int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st) {
+int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step = -1) {
   PassArgs<T> aa = a;
   aa.mode = pa_mode;
-  HIP_TRY(launch_pass_a<T>(aa, st));
-  HIP_TRY(launch_pass_b<T>(a, st));
-  HIP_TRY(launch_pass_c<T>(a, st));
+  const bool dbl = sizeof(T) == 8;
+  PassBytes pb = pass_bytes(a.g, sizeof(cplx<T>));
+  const double vec = (double)a.g.n * sizeof(cplx<T>);
+  if (a.mode == PC_GREEN || a.mode == PC_CONV) pb.c -= vec;  // x is not read
+  if (a.mode == PC_ADJ_RESID) pb.c += vec;                   // rhs is read
+  // the contrast grid is shared by the systems of a launch: counted once
+  const double grid = (double)a.g.P * a.g.P * a.g.P * sizeof(T);
+  const double nb_b = step >= 0 ? 0.0 : nwork * (pb.b - grid) + grid;
+  HIP_TRY(timed(K_PASS_A, dbl, step >= 0 ? 0.0 : nwork * pb.a, step, pb.a, st, [&] { return launch_pass_a<T>(aa, st); }));
+  HIP_TRY(timed(K_PASS_B, dbl, nb_b, step, pb.b - grid + grid / std::max(1, a.g.S), st, [&] { return launch_pass_b<T>(a, st); }));
+  HIP_TRY(timed(K_PASS_C, dbl, step >= 0 ? 0.0 : nwork * pb.c, step, pb.c, st, [&] { return launch_pass_c<T>(a, st); }));
   return GSM_OK;
 }
+
+constexpr int kLead = 2;  // Arnoldi steps the host may run ahead of the device
 
 // The solve loop of one group.
 template <typename T>
 int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const gsm_solver_opts* so,
-              const Grid* grid, hipStream_t st) {
+              const Grid* grid, hipStream_t st, bool adjoint) {
   const int S = g.shape.S;
   const long long n = g.shape.n;
   const int m = so->restart;
   const bool fp64 = sizeof(T) == 8;
-  int rc = ensure_flags(plan, S);
+  const size_t vb = sizeof(cplx<T>);
+  int rc = ensure_flags(plan, 2 * S);
   if (rc) return rc;
+  g_prof.group_tag++;
   HIP_TRY(launch_state_init(g.shape, g.st, g.x64, nullptr, st));
   if (so->x0) {
     for (int k = 0; k < S; ++k)
@@ -478,6 +600,7 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
   }
   KrylovArgs<double> k64 = krylov_args<double>(g, m);
   KrylovArgs<T> kt = krylov_args<T>(g, m);
+  kt.host_inner = plan->h_inner;
   PassArgs<double> r = pass_args<double>(g, grid);
   r.g.nblk_c = nblk_c_for(g.shape, true);
   k64.g.nblk_c = r.g.nblk_c;
@@ -485,37 +608,60 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
   r.xs = n;
   r.y = g.r64;
   r.ys = n;
-  r.mode = PC_RESID;
+  // forward: A = I - B with B = G V; adjoint: A^H = I - B^H with B^H = V G
+  // (G real symmetric, V Hermitian for real eps), i.e. the Green tensor is
+  // applied by pass A before the convolution
+  r.mode = adjoint ? PC_ADJ_RESID : PC_RESID;
+  r.rhs = g.rhs64;
+  r.rs = n;
   r.gate = GATE_OUTER;
+  const int r_pa = adjoint ? PA_GREEN_PRE : 0;
   PassArgs<T> p = pass_args<T>(g, grid);
   p.g.nblk_c = nblk_c_for(g.shape, fp64);
   p.xs = (long long)(m + 1) * n;
   p.ys = p.xs;
-  p.mode = PC_FWD;
+  p.mode = adjoint ? PC_CONV : PC_GREEN;  // the Arnoldi process runs on B (or B^H)
   p.gate = GATE_INNER;
   cplx<T>* V = (cplx<T>*)g.V;
   const int cap = so->max_refine + 2;
+  int n_outer = S;  // systems still refining (known at each synchronisation)
+  const double vecb = (double)n * vb;
   for (int outer = 0; outer < cap; ++outer) {
-    rc = apply_passes<double>(r, 0, st);
+    rc = apply_passes<double>(r, r_pa, st, n_outer);
     if (rc) return rc;
-    HIP_TRY(launch_resid_finalize(k64, fp64 ? 1 : 0, g.flags, st));
-    HIP_TRY(hipMemcpyAsync(plan->h_flags, g.flags, S * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(timed(K_FINAL, true, 0.0, -1, 0.0, st, [&] { return launch_resid_finalize(k64, fp64 ? 1 : 0, g.flags, st); }));
+    HIP_TRY(hipMemcpyAsync(plan->h_flags, g.flags, 2 * S * sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    bool any = false;
-    for (int s = 0; s < S; ++s) any |= plan->h_flags[s] != 0;
-    if (!any) break;
-    HIP_TRY(launch_cast_v0<T>(kt, st));
+    prof_resolve(plan->h_flags + S, S, n, vb);
+    n_outer = 0;
+    for (int s = 0; s < S; ++s) n_outer += plan->h_flags[s] != 0;
+    if (!n_outer) break;
+    HIP_TRY(timed(K_CAST, fp64, n_outer * (n * sizeof(double2) + vecb), -1, 0.0, st,
+                  [&] { return launch_cast_v0<T>(kt, st); }));
+    // Issue the Arnoldi steps of one cycle, staying at most kLead steps ahead
+    // of the device: after step j the host waits for step j - kLead and
+    // stops as soon as every system's cycle has ended (the Givens kernel
+    // writes the per-system flags to pinned host memory).
     for (int j = 0; j < m; ++j) {
       p.x = V + (long long)j * n;
       p.y = V + (long long)(j + 1) * n;
-      rc = apply_passes<T>(p, j > 0 ? PA_NORMALIZE : 0, st);
+      rc = apply_passes<T>(p, r_pa | (j > 0 ? PA_NORMALIZE : 0), st, 0, j);
       if (rc) return rc;
-      HIP_TRY(launch_gs_dot<T>(kt, j, st));
-      HIP_TRY(launch_gs_update1<T>(kt, j, st));
-      HIP_TRY(launch_gs_update2<T>(kt, j, st));
-      HIP_TRY(launch_givens<T>(kt, j, st));
+      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, 0, st); }));
+      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, 0, st); }));
+      // second pass: only the systems whose first pass asked for it do work
+      // (their count is not known on the host, so no bytes are attributed)
+      HIP_TRY(timed(K_CGS_DOT2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_dot<T>(kt, j, 1, st); }));
+      HIP_TRY(timed(K_CGS_UPD2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_update<T>(kt, j, 1, st); }));
+      HIP_TRY(hipEventRecord(plan->step_ev[j], st));
+      if (j >= kLead) {
+        HIP_TRY(hipEventSynchronize(plan->step_ev[j - kLead]));
+        bool running = false;
+        for (int s = 0; s < S && !running; ++s) running = plan->h_inner[s] != 0;
+        if (!running) break;
+      }
     }
-    HIP_TRY(launch_lsq_update<T>(kt, st));
+    HIP_TRY(timed(K_LSQ, fp64, 0.0, -2, 0.0, st, [&] { return launch_lsq_update<T>(kt, st); }));
   }
   return GSM_OK;
 }
@@ -527,6 +673,7 @@ __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, S
   e.status = st[s].status;
   e.iters = st[s].iters;
   e.refinements = st[s].refinements;
+  e.reorth = st[s].nreorth;
   e.rel = st[s].rel;
   const long long i0 = ((long long)g.M[2] * g.N1[1] + g.M[1]) * g.N1[0] + g.M[0];
   const long long cs = (long long)g.npencil * g.N1[2];
@@ -539,8 +686,9 @@ __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, S
 
 int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& groups, const gsm_solver_opts* so,
               void* ws, size_t ws_bytes, double* E_out, bool out_host, std::vector<SysExport>& exp,
-              hipStream_t st) {
+              hipStream_t st, const double* rhs = nullptr) {
   const bool fp64 = so->precision == GSM_FP64;
+  const bool adjoint = rhs != nullptr;
   int rc = carve(groups, ws, ws_bytes, so->restart, fp64);
   if (rc) return rc;
   exp.assign(sys.size(), SysExport{});
@@ -553,8 +701,17 @@ int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& g
     std::vector<SysParam> par;
     for (int si : g.sys) par.push_back(sys[si].par);
     HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
+    if (adjoint) {
+      for (int k = 0; k < g.shape.S; ++k) {
+        const SysDesc& s = sys[g.sys[k]];
+        HIP_TRY(hipMemcpyAsync(g.rhs64 + (long long)k * g.shape.n, rhs + 2 * s.out_off, s.n * sizeof(double2),
+                               hipMemcpyDeviceToDevice, st));
+      }
+      HIP_TRY(launch_rhs_norm(g.shape, g.rhs64, g.par, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
-    rc = fp64 ? run_group<double>(plan, g, sys, so, grid, st) : run_group<float>(plan, g, sys, so, grid, st);
+    rc = fp64 ? run_group<double>(plan, g, sys, so, grid, st, adjoint)
+              : run_group<float>(plan, g, sys, so, grid, st, adjoint);
     if (rc) break;
     for (int k = 0; k < g.shape.S; ++k) {
       const SysDesc& s = sys[g.sys[k]];
@@ -580,6 +737,8 @@ void fill_info(const std::vector<SysDesc>& sys, const std::vector<SysExport>& ex
     f.iterations = exp[i].iters;
     f.refinements = exp[i].refinements;
     f.fft_size = sys[i].P;
+    f.reorth = exp[i].reorth;
+    f.reserved = 0;
     f.rel_residual = exp[i].rel;
     f.eps_b = sys[i].par.eps_b;
     if (f.status == GSM_W_NOT_CONVERGED) *worst = GSM_W_NOT_CONVERGED;
@@ -747,6 +906,9 @@ int gsm_plan_destroy(gsm_plan_t p) {
   }
   hipFree(p->d_coef);
   if (p->h_flags) hipHostFree(p->h_flags);
+  if (p->h_inner) hipHostFree(p->h_inner);
+  for (int j = 0; j < kMaxRestart; ++j)
+    if (p->step_ev[j]) hipEventDestroy(p->step_ev[j]);
   delete p;
   return GSM_OK;
 }
@@ -865,7 +1027,7 @@ int gsm_apply(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t pr
       a.xs = a.ys = g.shape.n;
       a.mode = pc_mode;
       a.gate = GATE_NONE;
-      if ((rc = apply_passes<double>(a, pa_mode, st))) return rc;
+      if ((rc = apply_passes<double>(a, pa_mode, st, g.shape.S))) return rc;
     } else {
       PassArgs<float> a = pass_args<float>(g, grid);
       a.g.nblk_c = nblk_c_for(g.shape, false);
@@ -874,7 +1036,7 @@ int gsm_apply(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t pr
       a.xs = a.ys = g.shape.n;
       a.mode = pc_mode;
       a.gate = GATE_NONE;
-      if ((rc = apply_passes<float>(a, pa_mode, st))) return rc;
+      if ((rc = apply_passes<float>(a, pa_mode, st, g.shape.S))) return rc;
     }
     for (int k = 0; k < g.shape.S; ++k) {
       const SysDesc& s = sys[g.sys[k]];
@@ -951,14 +1113,220 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
   return worst;
 }
 
-int gsm_solve_adjoint(gsm_plan_t, int32_t, const gsm_instance*, const gsm_solver_opts*, const double*, double*,
-                      void*, size_t, gsm_solve_info*, void*) {
-  return fail(GSM_E_UNSUPPORTED, "gsm_solve_adjoint: not built yet");
+int gsm_profile_begin(void) {
+  g_prof.on = true;
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  return GSM_OK;
 }
 
-int gsm_eff_tensor_vjp(gsm_plan_t, int32_t, const gsm_instance*, const gsm_solver_opts*, const double*,
-                       const double*, const double*, double*, void*, size_t, gsm_solve_info*, void*) {
-  return fail(GSM_E_UNSUPPORTED, "gsm_eff_tensor_vjp: not built yet");
+int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out) {
+  if (!g_prof.on) return fail(GSM_E_ARG, "profiling was not started");
+  g_prof.on = false;
+  HIP_TRY(hipDeviceSynchronize());
+  std::vector<gsm_kernel_stat> st(2 * K_NBASE);
+  for (int c = 0; c < 2 * K_NBASE; ++c) {
+    std::memset(&st[c], 0, sizeof st[c]);
+    snprintf(st[c].name, sizeof st[c].name, "%s_%s", kClassNames[c / 2], (c & 1) ? "c128" : "c64");
+  }
+  for (auto& r : g_prof.recs) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+    st[r.cls].launches += 1;
+    st[r.cls].ms += ms;
+    st[r.cls].bytes += r.step == -1 ? r.bytes : 0.0;
+  }
+  g_prof.recs.clear();
+  g_prof.used = 0;
+  int k = 0;
+  for (int c = 0; c < 2 * K_NBASE; ++c)
+    if (st[c].launches > 0) {
+      if (out && k < max) out[k] = st[c];
+      ++k;
+    }
+  if (n_out) *n_out = k;
+  return GSM_OK;
+}
+
+int gsm_solve_adjoint(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const gsm_solver_opts* so,
+                      const double* rhs, double* lambda_out, void* ws, size_t ws_bytes, gsm_solve_info* info,
+                      void* stream) {
+  if (!p || !inst || n_inst < 1 || !rhs || !lambda_out || !info)
+    return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  if ((rc = set_device(p))) return rc;
+  std::vector<SysDesc> sys;
+  if ((rc = build_systems(p, n_inst, inst, so, false, sys))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys, groups);
+  std::vector<SysExport> exp;
+  rc = solve_all(p, sys, groups, so, ws, ws_bytes, lambda_out, (so->flags & GSM_OUT_HOST) != 0, exp,
+                 (hipStream_t)stream, rhs);
+  if (rc) return rc;
+  int worst = GSM_OK;
+  fill_info(sys, exp, info, &worst);
+  return worst;
+}
+
+namespace {
+
+// Zero-padded inverse DFT of one component block [N1z][N1y][N1x] onto P^3.
+int expand3(const double2* in, const int M[3], int P, double2* t1, double2* t2, double2* out, hipStream_t st) {
+  const int N1[3] = {2 * M[0] + 1, 2 * M[1] + 1, 2 * M[2] + 1};
+  HIP_TRY(launch_dft_axis(in, t1, N1[2] * N1[1], N1[0], P, 1, -M[0], 0, P, +1, st));
+  HIP_TRY(launch_dft_axis(t1, t2, N1[2], N1[1], P, P, -M[1], 0, P, +1, st));
+  HIP_TRY(launch_dft_axis(t2, out, 1, N1[2], P, P * P, -M[2], 0, P, +1, st));
+  return GSM_OK;
+}
+
+using cplxd = std::complex<double>;
+
+void inv3(const cplxd a[3][3], cplxd inv[3][3], cplxd* det_out) {
+  const cplxd det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) - a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                    a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+      inv[r][c] = (a[r1][c1] * a[r2][c2] - a[r1][c2] * a[r2][c1]) / det;
+    }
+  *det_out = det;
+}
+
+}  // namespace
+
+int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const gsm_solver_opts* so,
+                       const double* E_save, const double* eps_eff, const double* gbar, double* grad_vox, void* ws,
+                       size_t ws_bytes, gsm_solve_info* info, void* stream) {
+  if (!p || !inst || n_inst < 1 || !E_save || !eps_eff || !gbar || !grad_vox || !info)
+    return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  if ((rc = set_device(p))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<SysDesc> sys;
+  if ((rc = build_systems(p, n_inst, inst, so, true, sys))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys, groups);
+  long long total = 0;
+  for (auto& s : sys) total += s.n;
+  double2 *rhs = nullptr, *lam = nullptr;
+  HIP_TRY(hipMalloc(&rhs, total * sizeof(double2)));
+  HIP_TRY(hipMalloc(&lam, total * sizeof(double2)));
+  std::vector<AdjInst> ais(n_inst);
+  auto cleanup = [&](int code) {
+    hipFree(rhs);
+    hipFree(lam);
+    return code;
+  };
+  const double2* E = (const double2*)E_save;
+  for (int i = 0; i < n_inst; ++i) {
+    const SysDesc& s0 = sys[3 * i];
+    const long long N = s0.n / 3;
+    const long long i0 = ((long long)s0.M[2] * (2 * s0.M[1] + 1) + s0.M[1]) * (2 * s0.M[0] + 1) + s0.M[0];
+    cplxd E0[3][3], E0inv[3][3], det, ee[3][3], gb[3][3];
+    for (int d = 0; d < 3; ++d)
+      for (int a = 0; a < 3; ++a) {
+        double2 v;
+        if (hipMemcpy(&v, E + sys[3 * i + d].out_off + a * N + i0, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
+          return cleanup(fail(GSM_E_DEVICE, "reading the saved fields failed"));
+        E0[a][d] = cplxd(v.x, v.y);
+      }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        ee[r][c] = cplxd(eps_eff[(9 * i + 3 * r + c) * 2], eps_eff[(9 * i + 3 * r + c) * 2 + 1]);
+        gb[r][c] = cplxd(gbar[(9 * i + 3 * r + c) * 2], gbar[(9 * i + 3 * r + c) * 2 + 1]);
+      }
+    inv3(E0, E0inv, &det);
+    if (!(std::abs(det) > 0)) return cleanup(fail(GSM_E_SINGULAR, "instance %d: E0 is singular", i));
+    AdjInst& ai = ais[i];
+    std::memset(&ai, 0, sizeof ai);
+    for (int a = 0; a < 3; ++a) {
+      ai.M[a] = s0.M[a];
+      ai.N1[a] = 2 * s0.M[a] + 1;
+      ai.mmax[a] = p->mmax[a];
+      ai.q0[a] = s0.par.q0[a];
+      ai.b[a] = s0.par.b[a];
+    }
+    ai.n = s0.n;
+    ai.eps_b = s0.par.eps_b;
+    // W = Gbar E0^-H: column p is w_p; u_p = eps_eff^H w_p
+    for (int pp = 0; pp < 3; ++pp) {
+      cplxd w[3];
+      for (int a = 0; a < 3; ++a) {
+        w[a] = 0;
+        for (int k = 0; k < 3; ++k) w[a] += gb[a][k] * std::conj(E0inv[pp][k]);
+        ai.w[pp][a] = make_double2(w[a].real(), w[a].imag());
+      }
+      for (int a = 0; a < 3; ++a) {
+        cplxd u = 0;
+        for (int k = 0; k < 3; ++k) u += std::conj(ee[k][a]) * w[k];
+        ai.u[pp][a] = make_double2(u.real(), u.imag());
+      }
+    }
+    if (hipSuccess != launch_adjoint_rhs(p->d_coef, ai, rhs + s0.out_off, st))
+      return cleanup(fail(GSM_E_DEVICE, "adjoint right-hand side launch failed"));
+  }
+  std::vector<SysExport> exp;
+  rc = solve_all(p, sys, groups, so, ws, ws_bytes, (double*)lam, false, exp, st, (const double*)rhs);
+  if (rc) return cleanup(rc);
+  const long long nvox = (long long)p->vox[0] * p->vox[1] * p->vox[2];
+  for (int i = 0; i < n_inst; ++i) {
+    const SysDesc& s0 = sys[3 * i];
+    const AdjInst& ai = ais[i];
+    const int P = s0.P;
+    const long long P3 = (long long)P * P * P;
+    const long long N = s0.n / 3;
+    const int nc[3] = {4 * ai.M[0] + 1, 4 * ai.M[1] + 1, 4 * ai.M[2] + 1};
+    const long long ncn = (long long)nc[0] * nc[1] * nc[2];
+    double2 *t1 = nullptr, *t2 = nullptr, *ah = nullptr, *eh = nullptr, *Y = nullptr, *X = nullptr, *gv = nullptr;
+    auto run = [&]() -> int {
+      const long long tsz = std::max<long long>({(long long)P * P * P, (long long)ai.N1[2] * ai.N1[1] * P,
+                                                  (long long)ai.N1[2] * P * P, (long long)P * P * nc[0],
+                                                  (long long)P * nc[1] * nc[0], (long long)nc[2] * nc[1] * p->vox[0],
+                                                  (long long)nc[2] * p->vox[1] * p->vox[0]});
+      HIP_TRY(hipMalloc(&t1, tsz * sizeof(double2)));
+      HIP_TRY(hipMalloc(&t2, tsz * sizeof(double2)));
+      HIP_TRY(hipMalloc(&ah, P3 * sizeof(double2)));
+      HIP_TRY(hipMalloc(&eh, P3 * sizeof(double2)));
+      HIP_TRY(hipMalloc(&Y, P3 * sizeof(double2)));
+      HIP_TRY(hipMalloc(&X, ncn * sizeof(double2)));
+      HIP_TRY(hipMalloc(&gv, std::max(nvox, ncn) * sizeof(double2)));
+      HIP_TRY(hipMemsetAsync(Y, 0, P3 * sizeof(double2), st));
+      HIP_TRY(launch_adjoint_weight(ai, lam + s0.out_off, st));
+      for (int pp = 0; pp < 3; ++pp)
+        for (int a = 0; a < 3; ++a) {
+          int r2;
+          if ((r2 = expand3(lam + s0.out_off + pp * s0.n + a * N, ai.M, P, t1, t2, ah, st))) return r2;
+          if ((r2 = expand3(E + s0.out_off + pp * s0.n + a * N, ai.M, P, t1, t2, eh, st))) return r2;
+          HIP_TRY(launch_conj_mul_acc(ah, eh, Y, P3, st));
+        }
+      // X_n = (1/P^3) sum_r Y(r) e^{+2 pi i n.r / P}, |n_a| <= 2 M_a (the 1/P^3 is applied at the end)
+      HIP_TRY(launch_dft_axis(Y, t1, P * P, P, nc[0], 1, 0, -2 * ai.M[0], P, +1, st));
+      HIP_TRY(launch_dft_axis(t1, t2, P, P, nc[1], nc[0], 0, -2 * ai.M[1], P, +1, st));
+      HIP_TRY(launch_dft_axis(t2, X, 1, P, nc[2], nc[1] * nc[0], 0, -2 * ai.M[2], P, +1, st));
+      // times the exact image of one voxel box, then sum_n e^{-2 pi i n.v / V}
+      HIP_TRY(launch_box_factor(X, nc, p->vox, st));
+      HIP_TRY(launch_dft_axis(X, t1, nc[2] * nc[1], nc[0], p->vox[0], 1, -2 * ai.M[0], 0, p->vox[0], -1, st));
+      HIP_TRY(launch_dft_axis(t1, t2, nc[2], nc[1], p->vox[1], p->vox[0], -2 * ai.M[1], 0, p->vox[1], -1, st));
+      HIP_TRY(launch_dft_axis(t2, gv, 1, nc[2], p->vox[2], p->vox[1] * p->vox[0], -2 * ai.M[2], 0, p->vox[2], -1, st));
+      HIP_TRY(launch_acc_real(gv, grad_vox, nvox, 2.0 / (double)P3, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      return GSM_OK;
+    };
+    rc = run();
+    hipFree(t1);
+    hipFree(t2);
+    hipFree(ah);
+    hipFree(eh);
+    hipFree(Y);
+    hipFree(X);
+    hipFree(gv);
+    if (rc) return cleanup(rc);
+  }
+  int worst = GSM_OK;
+  fill_info(sys, exp, info, &worst);
+  return cleanup(worst);
 }
 
 }  // extern "C"

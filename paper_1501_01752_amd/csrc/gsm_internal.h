@@ -42,6 +42,10 @@ struct SysState {
   int iters;         // total Krylov iterations
   int refinements;   // FP64 residual evaluations
   int status;        // 0 running/converged, 1 not converged
+  int reorth;        // the current step needs a second Gram-Schmidt pass
+  int gs_count;      // blocks done with the current Gram-Schmidt update (last-block test)
+  int nreorth;       // second passes made (diagnostics)
+  int dot_count;     // blocks done with the current dot-product pass (last-block test)
   int pad[2];
   double rho;        // ||r|| of the last FP64 residual
   double rel;        // rho / bnorm
@@ -55,8 +59,8 @@ struct SysState {
   double cs[kMaxRestart];
   double2 sn[kMaxRestart];
   double2 y[kMaxRestart];
-  double2 h1[kMaxRestart + 1];
-  double2 h2[kMaxRestart + 1];
+  double2 h1[kMaxRestart + 1];   // first-pass coefficients of the current step
+  double2 hw[kMaxRestart + 2];   // reduced Q^H w of the pass in flight, then ||w||^2
 };
 
 // Shape of a group: systems sharing (M, P).
@@ -75,7 +79,10 @@ struct GroupShape {
 // pass A modes
 enum { PA_NORMALIZE = 1, PA_GREEN_PRE = 2 };
 // pass C modes
-enum { PC_FWD = 0, PC_RESID = 1, PC_ADJ = 2, PC_ADJ_RESID = 3, PC_CONV = 4 };
+// PC_FWD y = x - G w; PC_RESID r = b - (x - G w) and |r|^2; PC_ADJ y = x - w
+// (Green applied in pass A); PC_ADJ_RESID r = rhs - (x - w); PC_CONV y = w;
+// PC_GREEN y = G w (the part B = G V of A = I - B, x not read).
+enum { PC_FWD = 0, PC_RESID = 1, PC_ADJ = 2, PC_ADJ_RESID = 3, PC_CONV = 4, PC_GREEN = 5 };
 // gating of blocks by state
 enum { GATE_NONE = 0, GATE_INNER = 1, GATE_OUTER = 2 };
 
@@ -110,22 +117,37 @@ struct KrylovArgs {
   SysState* st;
   cplx<T>* V;          // basis [S][restart+1][n]
   int restart;
-  double2* part1;      // [S][nchunk][restart+1]
-  double2* part2;      // [S][nchunk][restart+1]
+  double2* part1;      // [S][nchunk][restart+2] Gram-Schmidt partial sums
   double* partn;       // [S][nchunk]
   double2* x64;        // [S][n] FP64 iterate
   double2* r64;        // [S][n] FP64 residual
   double* partc;       // [S][nblk_c] pass C residual partials
+  int* host_inner;     // pinned host flags: cycle still running, per system (may be null)
 };
-template <typename T> hipError_t launch_gs_dot(const KrylovArgs<T>& a, int j, hipStream_t s);
-template <typename T> hipError_t launch_gs_update1(const KrylovArgs<T>& a, int j, hipStream_t s);
-template <typename T> hipError_t launch_gs_update2(const KrylovArgs<T>& a, int j, hipStream_t s);
-template <typename T> hipError_t launch_givens(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_cgs_dot(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
+template <typename T> hipError_t launch_cgs_update(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
 template <typename T> hipError_t launch_lsq_update(const KrylovArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_cast_v0(const KrylovArgs<T>& a, hipStream_t s);
 hipError_t launch_resid_finalize(const KrylovArgs<double>& a, int fp64_inner, int* flags, hipStream_t s);
 hipError_t launch_state_init(const GroupShape& g, SysState* st, double2* x64, const double2* x0,
                              hipStream_t s);
+
+// ---- adjoint of the effective tensor (adjoint.inc) ----
+struct AdjInst {
+  int M[3];
+  int N1[3];
+  long long n;          // 3 * N1^3
+  int mmax[3];          // plan order bounds (coefficient array is (4 mmax + 1)^3)
+  double q0[3], b[3];
+  double eps_b;
+  double2 w[3][3];      // w_p, p = drive
+  double2 u[3][3];      // eps_eff^H w_p
+};
+hipError_t launch_adjoint_rhs(const double2* coef, const AdjInst& ai, double2* rhs, hipStream_t s);
+hipError_t launch_adjoint_weight(const AdjInst& ai, double2* lam, hipStream_t s);
+hipError_t launch_conj_mul_acc(const double2* a, const double2* e, double2* y, long long n, hipStream_t s);
+hipError_t launch_acc_real(const double2* in, double* out, long long n, double scale, hipStream_t s);
+hipError_t launch_rhs_norm(const GroupShape& g, const double2* rhs, SysParam* par, hipStream_t s);
 
 // ---- plan kernels (plan.hip) ----
 // out[o][j][i] = sum_{k<nin} in[o][k][i] * exp(sign 2 pi i ((k+koff)(j+joff) mod Q) / Q)

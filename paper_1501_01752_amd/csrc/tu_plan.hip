@@ -1,2 +1,3 @@
-// plan-time kernels
+// plan-time kernels and the adjoint of the effective-tensor retrieval
 #include "plan.inc"
+#include "adjoint.inc"

@@ -44,10 +44,16 @@ class SolverOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("refinements", C.c_int32),
-                ("fft_size", C.c_int32), ("rel_residual", C.c_double), ("eps_b", C.c_double)]
+                ("fft_size", C.c_int32), ("reorth", C.c_int32), ("reserved", C.c_int32),
+                ("rel_residual", C.c_double), ("eps_b", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double)]
 
 
 class GsmError(RuntimeError):
@@ -87,6 +93,8 @@ _SIGS = {
                                      C.POINTER(SolverOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(SolveInfo),
                                      C.c_void_p]),
+    "gsm_profile_begin": (C.c_int, []),
+    "gsm_profile_end": (C.c_int, [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
 }
 
 
@@ -110,6 +118,19 @@ def _check(status, allow_warn=True):
     if status < 0 or (status > 0 and not allow_warn):
         raise GsmError(status, lib().gsm_last_error().decode())
     return status
+
+
+def profile_begin():
+    _check(lib().gsm_profile_begin())
+
+
+def profile_end():
+    """Per-kernel-class {launches, ms, bytes} since profile_begin()."""
+    out = (KernelStat * 64)()
+    n = C.c_int32()
+    _check(lib().gsm_profile_end(out, 64, C.byref(n)))
+    return {out[i].name.decode(): dict(launches=out[i].launches, ms=out[i].ms, bytes=out[i].bytes)
+            for i in range(min(n.value, 64))}
 
 
 def default_opts(**kw):
@@ -259,6 +280,38 @@ class Plan:
                                _stream(stream)))
         return y
 
+    def solve_adjoint(self, insts, rhs, opts=None, stream=None):
+        """lambda = A^-H rhs for every (instance, drive); rhs complex128 (device)."""
+        import torch
+        opts = opts or default_opts()
+        arr = instances_array(insts)
+        rhs = rhs.contiguous()
+        lam = torch.empty_like(rhs)
+        info = (SolveInfo * len(system_sizes(insts)))()
+        ws = self.workspace(insts, opts)
+        st = lib().gsm_solve_adjoint(self.handle, len(insts), arr, C.byref(opts), C.c_void_p(rhs.data_ptr()),
+                                     C.c_void_p(lam.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(), info,
+                                     _stream(stream))
+        _check(st)
+        return lam, [i.as_dict() for i in info], st
+
+    def eff_tensor_vjp(self, insts, E_save, eps_eff, gbar, opts=None, stream=None):
+        """dL/d eps_voxel (numpy, shape of the voxel body) for gbar = dL/d conj(eps_eff)."""
+        import torch
+        opts = opts or default_opts()
+        arr = instances_array(insts)
+        ee = np.ascontiguousarray(eps_eff, dtype=np.complex128)
+        gb = np.ascontiguousarray(gbar, dtype=np.complex128)
+        grad = torch.zeros(self.eps.size, dtype=torch.float64, device=f"cuda:{self.device}")
+        info = (SolveInfo * (3 * len(insts)))()
+        ws = self.workspace(insts, opts)
+        st = lib().gsm_eff_tensor_vjp(self.handle, len(insts), arr, C.byref(opts), C.c_void_p(E_save.data_ptr()),
+                                      ee.ctypes.data_as(C.c_void_p), gb.ctypes.data_as(C.c_void_p),
+                                      C.c_void_p(grad.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(), info,
+                                      _stream(stream))
+        _check(st)
+        return grad.reshape(self.eps.shape), [i.as_dict() for i in info], st
+
     def eff_tensor(self, insts, opts=None, save_fields=False, stream=None):
         """eps_eff = D0 E0^-1 per instance (numpy [n, 3, 3] complex128)."""
         import torch
@@ -277,3 +330,52 @@ class Plan:
                                   C.c_void_p(ws.data_ptr()), ws.numel(), info, _stream(stream))
         _check(st)
         return out, E, [i.as_dict() for i in info], st
+
+
+def _eff_tensor_function():
+    import torch
+
+    class EffTensorFn(torch.autograd.Function):
+        """eps_eff (complex128 [n_inst, 3, 3]) of a voxel permittivity tensor.
+
+        forward: builds a plan from eps (real, shape (Vz, Vy, Vx)) and calls
+        gsm_eff_tensor; backward: gsm_eff_tensor_vjp (three adjoint solves per
+        instance, real-space correlation, exact voxel-box images).  torch
+        passes grad = 2 dL/d conj(eps_eff) for a real loss, so gbar = grad / 2.
+        The basis permittivity is held fixed between forward and backward.
+        """
+
+        @staticmethod
+        def forward(ctx, eps, period, m_max, insts, opts):
+            e = eps.detach().cpu().numpy()
+            plan = Plan(e, period, m_max, device=eps.device.index or 0 if eps.is_cuda else 0)
+            fixed = []
+            for x in insts:
+                y = Instance()
+                C.pointer(y)[0] = x
+                if y.eps_b <= 0:
+                    y.eps_b = plan.basis_eps(y)
+                fixed.append(y)
+            ee, E, info, st = plan.eff_tensor(fixed, opts, save_fields=True)
+            ctx.plan, ctx.insts, ctx.opts, ctx.E, ctx.ee = plan, fixed, opts, E, ee
+            ctx.eps_device = eps.device
+            return torch.from_numpy(ee).to(eps.device)
+
+        @staticmethod
+        def backward(ctx, grad):
+            gbar = (grad.detach().cpu().numpy() / 2.0).astype(np.complex128)
+            g, _, _ = ctx.plan.eff_tensor_vjp(ctx.insts, ctx.E, ctx.ee, gbar, ctx.opts)
+            return g.to(ctx.eps_device), None, None, None, None
+
+    return EffTensorFn
+
+
+_EFF_FN = None
+
+
+def eff_tensor_fn():
+    """The torch.autograd.Function computing eps_eff from voxel permittivities."""
+    global _EFF_FN
+    if _EFF_FN is None:
+        _EFF_FN = _eff_tensor_function()
+    return _EFF_FN
