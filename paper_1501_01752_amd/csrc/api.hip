@@ -486,9 +486,11 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
 // that launch).  Systems that finish a Krylov cycle early are only known at
 // the next host synchronisation, so step launches are attributed then.
 
-enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_DOT2, K_CGS_UPD2, K_LSQ, K_CAST, K_FINAL, K_NBASE };
-const char* kClassNames[K_NBASE] = {"pass_a", "pass_b", "pass_c", "cgs_dot", "cgs_update",
-                                    "cgs_dot_2nd", "cgs_update_2nd", "lsq_update", "cast_v0", "resid_finalize"};
+enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_FIN, K_CGS_DOT2, K_CGS_UPD2, K_CGS_FIN2,
+              K_LSQ, K_CAST, K_FINAL, K_NBASE };
+const char* kClassNames[K_NBASE] = {"pass_a", "pass_b", "pass_c", "cgs_dot", "cgs_update", "cgs_finish",
+                                    "cgs_dot_2nd", "cgs_update_2nd", "cgs_finish_2nd", "lsq_update", "cast_v0",
+                                    "resid_finalize"};
 
 struct ProfRec {
   int cls;        // base class * 2 + (complex128 ? 1 : 0)
@@ -649,10 +651,12 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
       if (rc) return rc;
       HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, 0, st); }));
       HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, 0, st); }));
+      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, 0, st); }));
       // second pass: only the systems whose first pass asked for it do work
       // (their count is not known on the host, so no bytes are attributed)
       HIP_TRY(timed(K_CGS_DOT2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_dot<T>(kt, j, 1, st); }));
       HIP_TRY(timed(K_CGS_UPD2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_update<T>(kt, j, 1, st); }));
+      HIP_TRY(timed(K_CGS_FIN2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, 1, st); }));
       HIP_TRY(hipEventRecord(plan->step_ev[j], st));
       if (j >= kLead) {
         HIP_TRY(hipEventSynchronize(plan->step_ev[j - kLead]));

@@ -126,6 +126,7 @@ struct KrylovArgs {
 };
 template <typename T> hipError_t launch_cgs_dot(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
 template <typename T> hipError_t launch_cgs_update(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
+template <typename T> hipError_t launch_cgs_finish(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
 template <typename T> hipError_t launch_lsq_update(const KrylovArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_cast_v0(const KrylovArgs<T>& a, hipStream_t s);
 hipError_t launch_resid_finalize(const KrylovArgs<double>& a, int fp64_inner, int* flags, hipStream_t s);
