@@ -252,6 +252,7 @@ struct Group {
   double2* part1 = nullptr;
   double* partn = nullptr;
   double* partc = nullptr;
+  int* any_reorth = nullptr;  // [restart+1] per-step second-pass flags
 };
 
 struct SysExport {
@@ -366,6 +367,7 @@ size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c
   g.part1 = (double2*)take(S * g.shape.nchunk * (restart + 2) * sizeof(double2));
   g.partn = (double*)take(S * g.shape.nchunk * sizeof(double));
   g.partc = (double*)take(S * nblk_c * sizeof(double));
+  g.any_reorth = (int*)take((restart + 1) * sizeof(int));
   return off;
 }
 
@@ -476,6 +478,7 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
   k.x64 = g.x64;
   k.r64 = g.r64;
   k.partc = g.partc;
+  k.any_reorth = g.any_reorth;
   return k;
 }
 
@@ -486,11 +489,11 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
 // that launch).  Systems that finish a Krylov cycle early are only known at
 // the next host synchronisation, so step launches are attributed then.
 
-enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_FIN, K_CGS_DOT2, K_CGS_UPD2, K_CGS_FIN2,
-              K_LSQ, K_CAST, K_FINAL, K_NBASE };
-const char* kClassNames[K_NBASE] = {"pass_a", "pass_b", "pass_c", "cgs_dot", "cgs_update", "cgs_finish",
-                                    "cgs_dot_2nd", "cgs_update_2nd", "cgs_finish_2nd", "lsq_update", "cast_v0",
-                                    "resid_finalize"};
+enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_FIN, K_CGS_RE, K_LSQ, K_CAST, K_FINAL,
+              K_NBASE };
+const char* kClassNames[K_NBASE] = {"pass_a",          "pass_b",     "pass_c",  "cgs_dot",
+                                    "cgs_update",      "cgs_finish", "cgs_second_pass",
+                                    "lsq_update",      "cast_v0",    "resid_finalize"};
 
 struct ProfRec {
   int cls;        // base class * 2 + (complex128 ? 1 : 0)
@@ -649,14 +652,14 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
       p.y = V + (long long)(j + 1) * n;
       rc = apply_passes<T>(p, r_pa | (j > 0 ? PA_NORMALIZE : 0), st, 0, j);
       if (rc) return rc;
-      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, 0, st); }));
-      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, 0, st); }));
-      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, 0, st); }));
-      // second pass: only the systems whose first pass asked for it do work
-      // (their count is not known on the host, so no bytes are attributed)
-      HIP_TRY(timed(K_CGS_DOT2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_dot<T>(kt, j, 1, st); }));
-      HIP_TRY(timed(K_CGS_UPD2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_update<T>(kt, j, 1, st); }));
-      HIP_TRY(timed(K_CGS_FIN2, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, 1, st); }));
+      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, st); }));
+      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, st); }));
+      // finish: Givens step, unless the first pass removed nearly all of w;
+      // those systems get a second Gram-Schmidt pass, whose kernels return
+      // at once when no system of the group asked for one (its bytes are
+      // not attributed: the host does not know how often it runs)
+      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, st); }));
+      HIP_TRY(timed(K_CGS_RE, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_second_pass<T>(kt, j, st); }));
       HIP_TRY(hipEventRecord(plan->step_ev[j], st));
       if (j >= kLead) {
         HIP_TRY(hipEventSynchronize(plan->step_ev[j - kLead]));

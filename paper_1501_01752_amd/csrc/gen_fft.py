@@ -250,20 +250,25 @@ def codelet_specs():
     """
     specs = []
     pairs = set()
-    # transform size P with K = (P-1)//4 (R = 1) and the split halves (R = 2):
+    fulls = set()
+    # A length-P transform (orders |k| <= K = (P-1)//4) is split over R lanes
+    # of length N = P / R: at most 32 values per lane in complex64, 16 in
+    # complex128 (the kernels' rule).  When 2K+1 > N the orders fold and the
+    # lane runs a full length-N transform.
     for p in (4, 8, 16, 32, 64, 128):
         k = (p - 1) // 4
-        pairs.add((p, k))
-        if p >= 8:
-            pairs.add((p // 2, k))
+        for lane_max in (32, 16):
+            n = min(p, lane_max)
+            if 2 * k + 1 <= n:
+                pairs.add((n, k))
+            else:
+                fulls.add(n)
     for n, k in sorted(pairs):
-        if 2 * k + 1 > n:
-            continue
         i, o = expand_slots(n, k)
         specs.append((f'fft_e{n}_{k}', n, i, o, +1))
         i, o = crop_slots(n, k)
         specs.append((f'fft_c{n}_{k}', n, i, o, -1))
-    for n in (32,):
+    for n in sorted(fulls):
         specs.append((f'fft_fp{n}', n, list(range(n)), list(range(n)), +1))
         specs.append((f'fft_fm{n}', n, list(range(n)), list(range(n)), -1))
     return specs

@@ -59,8 +59,8 @@ struct SysState {
   double cs[kMaxRestart];
   double2 sn[kMaxRestart];
   double2 y[kMaxRestart];
-  double2 h1[kMaxRestart + 1];   // first-pass coefficients of the current step
-  double2 hw[kMaxRestart + 2];   // reduced Q^H w of the pass in flight, then ||w||^2
+  double2 hw[kMaxRestart + 2];   // first-pass Q^H w of the current step, then ||w||^2
+  double2 hw2[kMaxRestart + 2];  // second-pass coefficients (when one is made)
 };
 
 // Shape of a group: systems sharing (M, P).
@@ -123,10 +123,12 @@ struct KrylovArgs {
   double2* r64;        // [S][n] FP64 residual
   double* partc;       // [S][nblk_c] pass C residual partials
   int* host_inner;     // pinned host flags: cycle still running, per system (may be null)
+  int* any_reorth;     // [restart+1] per step: some system of the group needs a second pass
 };
-template <typename T> hipError_t launch_cgs_dot(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
-template <typename T> hipError_t launch_cgs_update(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
-template <typename T> hipError_t launch_cgs_finish(const KrylovArgs<T>& a, int j, int pass, hipStream_t s);
+template <typename T> hipError_t launch_cgs_dot(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_cgs_update(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_cgs_finish(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_cgs_second_pass(const KrylovArgs<T>& a, int j, hipStream_t s);
 template <typename T> hipError_t launch_lsq_update(const KrylovArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_cast_v0(const KrylovArgs<T>& a, hipStream_t s);
 hipError_t launch_resid_finalize(const KrylovArgs<double>& a, int fp64_inner, int* flags, hipStream_t s);
