@@ -32,7 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# published vector peaks (packed FP32 FMA on every lane; FP64 FMA)
+ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
 TOL = 1e-9
+CPU_SAMPLE_S = 10.0
 
 
 def parse():
@@ -45,6 +48,13 @@ def parse():
     ap.add_argument("--config-steps", type=int, default=5, help="steps of the 4-solve case")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--matvec-only", type=int, default=0, metavar="REPS",
+                    help="for hardware-counter runs: a 1 GiB device copy (calibration), then REPS "
+                         "batched operator applications of one body of the step in complex64 and "
+                         "REPS in complex128; prints their wall times and exits")
+    ap.add_argument("--profile", choices=("timed", "separate"), default="timed",
+                    help="record the per-launch hipEvents inside the timed steps, or in as many "
+                         "extra steps after them")
     return ap.parse_args()
 
 
@@ -91,25 +101,82 @@ def run_step(gsm, work, opts):
 
 
 def cpu_baseline(inputs):
-    """The oracle's FFT + GMRES route (FP64) on one solve of the sphere lattice
-    at M = 15, x drive, to the same 1e-9 residual."""
+    """The oracle's FFT + GMRES route (FP64) on the normal-incidence solves of
+    the step (sphere lattice and layered stack at M = 15, x and y drives, the
+    same 1e-9 residual), taken in turn until about CPU_SAMPLE_S seconds have
+    passed."""
     from oracle import gsm as O
-    w = inputs.sphere_lattice_m15()
-    lam, M = w["wavelength"], w["M"]
-    k = 2 * np.pi / lam * np.array([0.0, 0.0, 1.0])
-    c = O.box_image(w["eps"], tuple(2 * m for m in M))
-    q = O.harmonic_q(k, lam, w["period"], M)
-    eb = float(np.mean(w["eps"]))
+    cases = []
+    for w in (inputs.sphere_lattice_m15(), inputs.layered_stack_m15()):
+        lam, M = w["wavelength"], w["M"]
+        k = 2 * np.pi / lam * np.array([0.0, 0.0, 1.0])
+        c = O.box_image(w["eps"], tuple(2 * m for m in M))
+        q = O.harmonic_q(k, lam, w["period"], M)
+        eb = float(np.mean(w["eps"]))
+        for a in ((1.0, 0, 0), (0, 1.0, 0)):
+            cases.append((c, M, q, eb, np.array(a, complex)))
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
-    E, it = O.solve_fft_gmres(c, M, q, eb, np.array([1.0, 0, 0], complex), (64, 64, 64), rtol=TOL)
+    n = its = 0
+    while n == 0 or time.perf_counter() - t0 < CPU_SAMPLE_S:
+        c, M, q, eb, a = cases[n % len(cases)]
+        _, it = O.solve_fft_gmres(c, M, q, eb, a, (64, 64, 64), rtol=TOL)
+        n += 1
+        its += it
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {"value": 1.0 / wall, "unit": "solves/s", "cores": max(1, int(round(cpu / wall))),
+    return {"value": n / wall, "unit": "solves/s", "cores": max(1, int(round(cpu / wall))),
             "kind": "oracle",
-            "sample": f"1 solve (sphere lattice, M=15, x drive, FP64 numpy FFT + scipy GMRES(30) "
-                      f"to 1e-9), {it} iterations, {wall:.1f} s wall"}
+            "sample": f"{n} normal-incidence solves (sphere lattice and layered stack, M=15, x/y drives, "
+                      f"FP64 numpy FFT + scipy GMRES(30) to 1e-9), {its} iterations, {wall:.1f} s wall"}
+
+
+def matvec_only(gsm, body, reps):
+    """Copy calibration and bare operator applications (no solve)."""
+    import torch
+    plan, insts = body
+    out = {}
+    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_1GiB_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
+    del src, dst
+    n = sum(gsm.system_sizes(insts))
+    g = torch.Generator(device="cpu").manual_seed(11)
+    for prec, dt, tag in ((gsm.GSM_MIXED, torch.complex64, "c64"), (gsm.GSM_FP64, torch.complex128, "c128")):
+        x = torch.randn(n, dtype=dt, generator=g).to("cuda")
+        plan.apply(insts, x, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.apply(insts, x, precision=prec)
+        torch.cuda.synchronize()
+        out[f"apply_{tag}_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+    out["systems"] = len(gsm.system_sizes(insts))
+    print(json.dumps(out))
+
+
+def roofline_of(name, v):
+    """Roofline entry of one kernel class: HBM (algorithmic bytes) or vector
+    ALU (algorithmic flops), whichever bound the launches come closer to."""
+    sec = v["ms"] * 1e-3
+    gbs = v["bytes"] / sec / 1e9 if sec > 0 else 0.0
+    tfs = v.get("flops", 0.0) / sec / 1e12 if sec > 0 else 0.0
+    peak_alu = ALU_PEAK_TFLOPS["c128" if name.endswith("c128") else "c64"]
+    common = {"traffic": None, "kernel": name,
+              "avg_launch_us": round(v["ms"] * 1e3 / max(1, v["launches"]), 2)}
+    if tfs / peak_alu > gbs / HBM_PEAK_GBS:
+        return {"bound": "alu", "achieved": round(tfs, 2), "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": round(tfs / peak_alu, 4), **common,
+                "hbm": {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), **common}
 
 
 def main():
@@ -125,6 +192,9 @@ def main():
         print(json.dumps({"error": "no HIP device"}))
         sys.exit(1)
     work = build_workload(gsm, inputs, args.directions)
+    if args.matvec_only:
+        matvec_only(gsm, work[0], args.matvec_only)
+        return
     opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30)
     for _ in range(args.warmup):
         run_step(gsm, work, opts)
@@ -132,7 +202,8 @@ def main():
 
     for k in STATS:
         STATS[k] = 0
-    gsm.profile_begin()
+    if args.profile == "timed":
+        gsm.profile_begin()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total = 0
@@ -143,19 +214,21 @@ def main():
         worst = max(worst, w)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = gsm.profile_end()
     krylov = {k: round(STATS[k] / max(1, STATS["solves"]), 2) for k in ("iterations", "refinements", "reorth")}
+    if args.profile == "separate":
+        gsm.profile_begin()
+        for _ in range(args.steps):
+            run_step(gsm, work, opts)
+    prof = gsm.profile_end()
     dt = t1 - t0
     value = total / dt
 
     # dominant kernel class by time
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
-    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
-                "avg_launch_us": round(dom["ms"] * 1e3 / max(1, dom["launches"]), 2)}
+    roofline = roofline_of(dom_name, dom)
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None,
+                   "TFLOPs": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 and v["flops"] else None}
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
     # plain FP64 GPU solve of the same workload
@@ -191,7 +264,7 @@ def main():
         "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64+f64",
-        "data": "synthetic",
+        "data": "synthetic", "profile": args.profile,
         "config": {"workload": "31^3 orders (M=15), 64^3 FFT grid: sphere lattice (r=0.3 Lambda, eps 4, "
                                "64^3 voxels) + layered stack (f=0.4, eps 2.25/9), Lambda=0.3 lambda, "
                                f"2 transverse drives x (normal incidence + {args.directions} seeded directions) "

@@ -68,8 +68,10 @@ enum {
 
 /* precision of the Krylov iterations (the FP64 residual is always FP64) */
 enum { GSM_MIXED = 0, GSM_FP64 = 1 };
-/* Krylov method */
-enum { GSM_GMRES = 0 };
+/* Krylov method: restarted GMRES (default), or BiCGStab (two operator
+ * applications per iteration, six vectors per system; needs restart >= 5,
+ * which then only sizes the workspace) */
+enum { GSM_GMRES = 0, GSM_BICGSTAB = 1 };
 /* gsm_solver_opts.flags */
 enum { GSM_OUT_HOST = 1 /* E_out / eps_eff / grad are host pointers */ };
 /* gsm_apply modes */
@@ -111,7 +113,7 @@ typedef struct gsm_solver_opts {
   int32_t max_iter;   /* cap on Krylov iterations per system; default 5000 */
   int32_t max_refine; /* cap on FP64 residual evaluations per system; default 200 */
   int32_t precision;  /* GSM_MIXED (complex64 Krylov inside FP64 refinement) or GSM_FP64 */
-  int32_t method;     /* GSM_GMRES */
+  int32_t method;     /* GSM_GMRES or GSM_BICGSTAB */
   int32_t flags;      /* GSM_OUT_HOST */
   const double* x0;   /* NULL or an initial guess (device, layout of E_out) */
 } gsm_solver_opts;
@@ -244,6 +246,7 @@ typedef struct gsm_kernel_stat {
   int64_t launches;
   double ms;
   double bytes;
+  double flops;     /* algorithmic real floating-point operations (FFT passes) */
 } gsm_kernel_stat;
 
 /* Start collecting (clears earlier records).  Not thread-safe. */

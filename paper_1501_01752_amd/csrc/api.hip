@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/gsm.h"
+#include "fft_opcount.h"
 #include "gsm_internal.h"
 
 using namespace gsm;
@@ -137,7 +138,9 @@ int check_solver_opts(const gsm_solver_opts* s) {
   if (s->max_iter < 1) return fail(GSM_E_ARG, "max_iter must be >= 1");
   if (s->max_refine < 1) return fail(GSM_E_ARG, "max_refine must be >= 1");
   if (s->precision != GSM_MIXED && s->precision != GSM_FP64) return fail(GSM_E_ARG, "unknown precision %d", s->precision);
-  if (s->method != GSM_GMRES) return fail(GSM_E_ARG, "unknown method %d", s->method);
+  if (s->method != GSM_GMRES && s->method != GSM_BICGSTAB) return fail(GSM_E_ARG, "unknown method %d", s->method);
+  if (s->method == GSM_BICGSTAB && s->restart < 5)
+    return fail(GSM_E_ARG, "BiCGStab keeps six vectors per system: restart must be >= 5");
   if (s->flags & ~GSM_OUT_HOST) return fail(GSM_E_ARG, "unknown solver flags");
   return GSM_OK;
 }
@@ -490,10 +493,11 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
 // the next host synchronisation, so step launches are attributed then.
 
 enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_FIN, K_CGS_RE, K_LSQ, K_CAST, K_FINAL,
-              K_NBASE };
+              K_BICG_INIT, K_BICG_DOT, K_BICG_UPD, K_NBASE };
 const char* kClassNames[K_NBASE] = {"pass_a",          "pass_b",     "pass_c",  "cgs_dot",
                                     "cgs_update",      "cgs_finish", "cgs_second_pass",
-                                    "lsq_update",      "cast_v0",    "resid_finalize"};
+                                    "lsq_update",      "cast_v0",    "resid_finalize",
+                                    "bicg_init",       "bicg_dot",   "bicg_update"};
 
 struct ProfRec {
   int cls;        // base class * 2 + (complex128 ? 1 : 0)
@@ -502,6 +506,8 @@ struct ProfRec {
   int step;       // Arnoldi step (>= 0) to resolve later, -1 resolved, -2 lsq
   double unit;    // bytes per working system (step records)
   int group;
+  double flops;   // resolved algorithmic floating-point operations
+  double funit;   // operations per working system (step records)
 };
 
 struct Profiler {
@@ -522,9 +528,11 @@ hipEvent_t prof_event() {
 }
 
 template <class F>
-hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f) {
+hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f,
+                 double flops = 0.0, double funit = 0.0) {
   if (!g_prof.on) return f();
-  ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag};
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag,
+            flops, funit};
   if (r.a) hipEventRecord(r.a, st);
   const hipError_t e = f();
   if (r.b) hipEventRecord(r.b, st);
@@ -546,6 +554,7 @@ void prof_resolve(const int* jdone, int S, long long n, size_t vb) {
       int cnt = 0;
       for (int s = 0; s < S; ++s) cnt += jdone[s] > r.step;
       tot = cnt * r.unit;
+      r.flops = cnt * r.funit;
     }
     r.bytes = tot;
     r.step = -1;
@@ -565,25 +574,85 @@ PassBytes pass_bytes(const GroupShape& g, size_t bc) {
   return {vec + mid, 2 * mid + grid, mid + 2 * vec};
 }
 
+// Algorithmic floating-point operations of the three passes per system: the
+// pruned length-P transforms (their real add, sub and mul counts), the real
+// contrast multiply (2 per complex point) and, in pass C, the real symmetric
+// 3x3 Green tensor times the complex field plus the subtraction (36 per
+// harmonic).  Pass B expands x on N1y rows, then y on P columns, and crops
+// in the reverse order.
+PassBytes pass_flops(const GroupShape& g) {
+  const int lp = __builtin_ctz(g.P) - 2;
+  auto fe = [&](int ax) { return (double)kPrunedOps[lp][g.M[ax]][0]; };
+  auto fc = [&](int ax) { return (double)kPrunedOps[lp][g.M[ax]][1]; };
+  const double P = g.P, nx = g.N1[0], ny = g.N1[1], nz = g.N1[2];
+  const double plane = ny * (fe(0) + fc(0)) + P * (fe(1) + fc(1)) + 2.0 * P * P;
+  return {3.0 * nx * ny * fe(2), 3.0 * P * plane, 3.0 * nx * ny * fc(2) + 36.0 * nx * ny * nz};
+}
+
 template <typename T>
 int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step = -1) {
   PassArgs<T> aa = a;
   aa.mode = pa_mode;
   const bool dbl = sizeof(T) == 8;
   PassBytes pb = pass_bytes(a.g, sizeof(cplx<T>));
+  const PassBytes pf = pass_flops(a.g);
+  const double nf = step >= 0 ? 0.0 : (double)nwork;
   const double vec = (double)a.g.n * sizeof(cplx<T>);
   if (a.mode == PC_GREEN || a.mode == PC_CONV) pb.c -= vec;  // x is not read
   if (a.mode == PC_ADJ_RESID) pb.c += vec;                   // rhs is read
   // the contrast grid is shared by the systems of a launch: counted once
   const double grid = (double)a.g.P * a.g.P * a.g.P * sizeof(T);
   const double nb_b = step >= 0 ? 0.0 : nwork * (pb.b - grid) + grid;
-  HIP_TRY(timed(K_PASS_A, dbl, step >= 0 ? 0.0 : nwork * pb.a, step, pb.a, st, [&] { return launch_pass_a<T>(aa, st); }));
-  HIP_TRY(timed(K_PASS_B, dbl, nb_b, step, pb.b - grid + grid / std::max(1, a.g.S), st, [&] { return launch_pass_b<T>(a, st); }));
-  HIP_TRY(timed(K_PASS_C, dbl, step >= 0 ? 0.0 : nwork * pb.c, step, pb.c, st, [&] { return launch_pass_c<T>(a, st); }));
+  HIP_TRY(timed(K_PASS_A, dbl, step >= 0 ? 0.0 : nwork * pb.a, step, pb.a, st, [&] { return launch_pass_a<T>(aa, st); },
+                nf * pf.a, pf.a));
+  HIP_TRY(timed(K_PASS_B, dbl, nb_b, step, pb.b - grid + grid / std::max(1, a.g.S), st,
+                [&] { return launch_pass_b<T>(a, st); }, nf * pf.b, pf.b));
+  HIP_TRY(timed(K_PASS_C, dbl, step >= 0 ? 0.0 : nwork * pb.c, step, pb.c, st, [&] { return launch_pass_c<T>(a, st); },
+                nf * pf.c, pf.c));
   return GSM_OK;
 }
 
 constexpr int kLead = 2;  // Arnoldi steps the host may run ahead of the device
+
+// One BiCGStab cycle of a group (A d = r / rho from d = 0, x += rho d in
+// FP64 as it goes), issued like the Arnoldi steps: at most kLead iterations
+// ahead of the device, ending when every system's cycle has ended.
+template <typename T>
+int bicg_cycle(gsm_plan_s* plan, const KrylovArgs<T>& kt, PassArgs<T> pa, int r_pa, cplx<T>* V, int S,
+               long long n, const gsm_solver_opts* so, hipStream_t st) {
+  const bool fp64 = sizeof(T) == 8;
+  const double vecb = (double)n * sizeof(cplx<T>);
+  const int cap = std::max(1, so->max_iter / 2 + 1);
+  int n_act = 0;
+  for (int s = 0; s < S; ++s) n_act += plan->h_flags[s] != 0;
+  HIP_TRY(timed(K_BICG_INIT, fp64, n_act * (n * sizeof(double2) + 3 * vecb), -1, 0.0, st,
+                [&] { return launch_bicg<T>(kt, BICG_INIT, 0, cap, st); }));
+  for (int it = 0; it < cap; ++it) {
+    pa.x = V + BI_P * n;
+    pa.y = V + BI_V * n;
+    int rc = apply_passes<T>(pa, r_pa, st, 0, it);
+    if (rc) return rc;
+    HIP_TRY(timed(K_BICG_DOT, fp64, 0.0, it, 2 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_DOT_RV, it, cap, st); }));
+    HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 3 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_S, it, cap, st); }));
+    pa.x = V + BI_S * n;
+    pa.y = V + BI_T * n;
+    rc = apply_passes<T>(pa, r_pa, st, 0, it);
+    if (rc) return rc;
+    HIP_TRY(timed(K_BICG_DOT, fp64, 0.0, it, 2 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_DOT_TS, it, cap, st); }));
+    HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 5 * vecb + 2.0 * n * sizeof(double2), st,
+                  [&] { return launch_bicg<T>(kt, BICG_XR, it, cap, st); }));
+    HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 4 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_P, it, cap, st); }));
+    HIP_TRY(hipEventRecord(plan->step_ev[it % kMaxRestart], st));
+    if (it >= kLead) {
+      HIP_TRY(hipEventSynchronize(plan->step_ev[(it - kLead) % kMaxRestart]));
+      bool running = false;
+      for (int s = 0; s < S && !running; ++s) running = plan->h_inner[s] != 0;
+      if (!running) break;
+    }
+  }
+  HIP_TRY(launch_bicg<T>(kt, BICG_END, 0, cap, st));
+  return GSM_OK;
+}
 
 // The solve loop of one group.
 template <typename T>
@@ -627,6 +696,9 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
   p.ys = p.xs;
   p.mode = adjoint ? PC_CONV : PC_GREEN;  // the Arnoldi process runs on B (or B^H)
   p.gate = GATE_INNER;
+  PassArgs<T> pbi = p;                    // BiCGStab applies A (or A^H) itself
+  pbi.mode = adjoint ? PC_ADJ : PC_FWD;
+  const bool bicg = so->method == GSM_BICGSTAB;
   cplx<T>* V = (cplx<T>*)g.V;
   const int cap = so->max_refine + 2;
   int n_outer = S;  // systems still refining (known at each synchronisation)
@@ -641,6 +713,11 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
     n_outer = 0;
     for (int s = 0; s < S; ++s) n_outer += plan->h_flags[s] != 0;
     if (!n_outer) break;
+    if (bicg) {
+      rc = bicg_cycle<T>(plan, kt, pbi, r_pa, V, S, n, so, st);
+      if (rc) return rc;
+      continue;
+    }
     HIP_TRY(timed(K_CAST, fp64, n_outer * (n * sizeof(double2) + vecb), -1, 0.0, st,
                   [&] { return launch_cast_v0<T>(kt, st); }));
     // Issue the Arnoldi steps of one cycle, staying at most kLead steps ahead
@@ -1142,6 +1219,7 @@ int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out) {
     st[r.cls].launches += 1;
     st[r.cls].ms += ms;
     st[r.cls].bytes += r.step == -1 ? r.bytes : 0.0;
+    st[r.cls].flops += r.step == -1 ? r.flops : 0.0;
   }
   g_prof.recs.clear();
   g_prof.used = 0;

@@ -16,6 +16,7 @@ that works on register arrays, so every twiddle is a literal constant.
 Usage: gen_fft.py OUT_HEADER
 """
 import math
+import os
 import sys
 from fractions import Fraction
 
@@ -313,6 +314,34 @@ def main(path):
         out.append(twiddle_table(n))
     with open(path, 'w') as f:
         f.write('\n'.join(out))
+    with open(os.path.join(os.path.dirname(path), 'fft_opcount.h'), 'w') as f:
+        f.write(opcount_table())
+
+
+def opcount_table():
+    """Real operations (add, sub, mul each one) of the unsplit pruned length-P
+    transforms for orders |k| <= K: the algorithmic work of one expand and one
+    crop, for every supported P and every K <= (P - 1) / 4."""
+    lines = ['// Generated by gen_fft.py: real operations of pruned length-P DFTs. Do not edit.',
+             '#pragma once', '',
+             '// kPrunedOps[log2(P) - 2][K] = {expand (2K+1 -> P), crop (P -> 2K+1)}',
+             'static const int kPrunedOps[6][32][2] = {']
+    rows = []
+    for p in (4, 8, 16, 32, 64, 128):
+        vals = []
+        for k in range(32):
+            if k <= (p - 1) // 4:
+                i, o = expand_slots(p, k)
+                fe = emit('e', p, i, o, +1)[1]
+                i, o = crop_slots(p, k)
+                fc = emit('c', p, i, o, -1)[1]
+            else:
+                fe = fc = 0
+            vals.append(f'{{{fe}, {fc}}}')
+        rows.append('  {' + ', '.join(vals) + '}')
+    lines.append(',\n'.join(rows))
+    lines.append('};')
+    return '\n'.join(lines) + '\n'
 
 
 if __name__ == '__main__':

@@ -11,7 +11,7 @@ namespace gsm {
 constexpr int kMaxRestart = 64;   // largest Krylov dimension per cycle
 constexpr int kMaxOrder = 31;     // largest M_a (P = 128)
 constexpr int kGsThreads = 256;   // block size of the Gram-Schmidt kernels
-constexpr int kGsPerThread = 4;   // vector elements per thread in those kernels
+constexpr int kGsPerThread = 8;   // vector elements per thread in those kernels
 constexpr int kGsChunk = kGsThreads * kGsPerThread;
 
 template <typename T> struct cplx_t;
@@ -54,6 +54,9 @@ struct SysState {
   double xscale;     // factor applied to the Krylov correction (rho)
   double pad2;
   double2 w0[3];     // zeroth order of the contrast convolution (last FP64 pass)
+  double2 brho[2];   // BiCGStab: (rh, r) of iterations of even / odd index
+  double2 balpha;    // BiCGStab: alpha of the current iteration
+  double2 bomega;    // BiCGStab: omega of the current iteration
   double2 g[kMaxRestart + 1];
   double2 H[(kMaxRestart + 1) * kMaxRestart];  // column j at H[j * (kMaxRestart+1) + i]
   double cs[kMaxRestart];
@@ -131,6 +134,12 @@ template <typename T> hipError_t launch_cgs_finish(const KrylovArgs<T>& a, int j
 template <typename T> hipError_t launch_cgs_second_pass(const KrylovArgs<T>& a, int j, hipStream_t s);
 template <typename T> hipError_t launch_lsq_update(const KrylovArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_cast_v0(const KrylovArgs<T>& a, hipStream_t s);
+// BiCGStab kernels (bicgstab.inc), selected by `kernel`; its vectors sit in
+// these slots of the system's Krylov storage
+enum { BI_RH = 0, BI_R = 1, BI_P = 2, BI_V = 3, BI_S = 4, BI_T = 5 };
+enum { BICG_INIT, BICG_DOT_RV, BICG_S, BICG_DOT_TS, BICG_XR, BICG_P, BICG_END };
+template <typename T>
+hipError_t launch_bicg(const KrylovArgs<T>& a, int kernel, int it, int it_cap, hipStream_t s);
 hipError_t launch_resid_finalize(const KrylovArgs<double>& a, int fp64_inner, int* flags, hipStream_t s);
 hipError_t launch_state_init(const GroupShape& g, SysState* st, double2* x64, const double2* x0,
                              hipStream_t s);

@@ -17,7 +17,7 @@ GSM_OK, GSM_W_NOT_CONVERGED = 0, 1
 GSM_E_ARG, GSM_E_NONFINITE, GSM_E_NOMEM, GSM_E_DEVICE = -1, -2, -3, -4
 GSM_E_SINGULAR, GSM_E_WORKSPACE, GSM_E_UNSUPPORTED = -5, -6, -7
 GSM_MIXED, GSM_FP64 = 0, 1
-GSM_GMRES = 0
+GSM_GMRES, GSM_BICGSTAB = 0, 1
 GSM_OUT_HOST = 1
 GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT = 0, 1
 
@@ -53,7 +53,7 @@ class SolveInfo(C.Structure):
 
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("ms", C.c_double),
-                ("bytes", C.c_double)]
+                ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 class GsmError(RuntimeError):
@@ -129,7 +129,8 @@ def profile_end():
     out = (KernelStat * 64)()
     n = C.c_int32()
     _check(lib().gsm_profile_end(out, 64, C.byref(n)))
-    return {out[i].name.decode(): dict(launches=out[i].launches, ms=out[i].ms, bytes=out[i].bytes)
+    return {out[i].name.decode(): dict(launches=out[i].launches, ms=out[i].ms, bytes=out[i].bytes,
+                                      flops=out[i].flops)
             for i in range(min(n.value, 64))}
 
 
