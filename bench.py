@@ -13,13 +13,16 @@ product moves more than 1 GB, well beyond the 256 MB Infinity Cache.  The
 literal 4-solve case (D = 0: x and y drives at normal incidence only) is
 timed as well and reported as "as_configured".
 
-Prints one JSON line: value = solves/s over the timed steps, the roofline of
-the dominant kernel class (algorithmic bytes over the hipEvent-measured
-duration of its launches in the timed region), the plain FP64 GPU solve of
-the same workload, and the CPU oracle (FFT + SciPy GMRES, FP64) timed on a
-bounded sample.
+Prints one JSON line: value = solves/s over the timed steps; the roofline of
+the dominant kernel class (found in one extra profiled step before the timed
+ones): its algorithmic bytes or flops over the durations of its launches in
+the timed steps, each bracketed by a hipEvent pair on its own stream (only
+that class carries events there); the per-class table of the extra step; the
+plain FP64 GPU solve of the same workload; and the CPU oracle (FFT + SciPy
+GMRES, FP64) timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import resource
@@ -32,8 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# published vector peaks (packed FP32 FMA on every lane; FP64 FMA)
+# published vector peaks: FP32 counts packed FMAs on every lane, FP64 FMAs
 ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
+# the same chip without packed FP32 (the kernels are built with it off):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_UNPACKED_TFLOPS = {"c64": 78.6, "c128": 78.6}
 TOL = 1e-9
 CPU_SAMPLE_S = 10.0
 
@@ -52,9 +58,10 @@ def parse():
                     help="for hardware-counter runs: a 1 GiB device copy (calibration), then REPS "
                          "batched operator applications of one body of the step in complex64 and "
                          "REPS in complex128; prints their wall times and exits")
-    ap.add_argument("--profile", choices=("timed", "separate"), default="timed",
-                    help="record the per-launch hipEvents inside the timed steps, or in as many "
-                         "extra steps after them")
+    ap.add_argument("--profile", choices=("dominant", "all"), default="dominant",
+                    help="kernel classes whose launches carry hipEvent pairs in the timed steps: "
+                         "only the dominant one (found in one extra profiled step before them), "
+                         "or all of them")
     return ap.parse_args()
 
 
@@ -137,13 +144,14 @@ def matvec_only(gsm, body, reps):
     import torch
     plan, insts = body
     out = {}
-    src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    # a plain shader copy of 1 GiB (read 1 GiB, write 1 GiB): torch's
+    # elementwise negation of 2^28 float32 values
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    src.fill_(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(3):
-        dst.copy_(src)
+        torch.neg(src, out=dst)
     torch.cuda.synchronize()
     out["copy_1GiB_ms"] = round((time.perf_counter() - t0) / 3 * 1e3, 3)
     del src, dst
@@ -163,20 +171,52 @@ def matvec_only(gsm, body, reps):
 
 
 def roofline_of(name, v):
-    """Roofline entry of one kernel class: HBM (algorithmic bytes) or vector
-    ALU (algorithmic flops), whichever bound the launches come closer to."""
+    """Roofline entry of one kernel class.  The bound follows the algorithmic
+    intensity (flops per byte) against the ridge of the chip as this build
+    uses it (unpacked vector FMA rate over HBM bandwidth): vector ALU above
+    it, HBM below."""
     sec = v["ms"] * 1e-3
     gbs = v["bytes"] / sec / 1e9 if sec > 0 else 0.0
     tfs = v.get("flops", 0.0) / sec / 1e12 if sec > 0 else 0.0
-    peak_alu = ALU_PEAK_TFLOPS["c128" if name.endswith("c128") else "c64"]
+    prec = "c128" if name.endswith("c128") else "c64"
+    ridge = ALU_UNPACKED_TFLOPS[prec] * 1e3 / HBM_PEAK_GBS
     common = {"traffic": None, "kernel": name,
               "avg_launch_us": round(v["ms"] * 1e3 / max(1, v["launches"]), 2)}
-    if tfs / peak_alu > gbs / HBM_PEAK_GBS:
-        return {"bound": "alu", "achieved": round(tfs, 2), "peak": peak_alu, "unit": "TFLOP/s",
-                "frac": round(tfs / peak_alu, 4), **common,
+    if v["bytes"] > 0 and v.get("flops", 0.0) / v["bytes"] > ridge:
+        peak = ALU_PEAK_TFLOPS[prec]
+        return {"bound": "alu", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tfs / peak, 4), **common,
+                "peak_unpacked": ALU_UNPACKED_TFLOPS[prec],
+                "frac_unpacked": round(tfs / ALU_UNPACKED_TFLOPS[prec], 4),
                 "hbm": {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), **common}
+
+
+def counted_traffic(name):
+    """HBM bytes per launch of kernel class `name` from the committed
+    hardware-counter record (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel
+    calibration), or None when there is none or the kernel sources changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{name}_m15_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec
+
+
+def kernel_table(prof):
+    return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None,
+                "TFLOPs": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 and v["flops"] else None}
+            for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
 
 def main():
@@ -200,10 +240,17 @@ def main():
         run_step(gsm, work, opts)
     torch.cuda.synchronize()
 
+    # one extra step with every kernel class timed: the per-class table and
+    # the dominant class
+    gsm.profile_begin()
+    run_step(gsm, work, opts)
+    kernels = kernel_table(gsm.profile_end())
+    dom_name = next(iter(kernels))
+    dom_class = dom_name.rsplit("_", 1)[0]
+
     for k in STATS:
         STATS[k] = 0
-    if args.profile == "timed":
-        gsm.profile_begin()
+    gsm.profile_begin(only=dom_class if args.profile == "dominant" else None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total = 0
@@ -214,48 +261,48 @@ def main():
         worst = max(worst, w)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    krylov = {k: round(STATS[k] / max(1, STATS["solves"]), 2) for k in ("iterations", "refinements", "reorth")}
-    if args.profile == "separate":
-        gsm.profile_begin()
-        for _ in range(args.steps):
-            run_step(gsm, work, opts)
     prof = gsm.profile_end()
+    krylov = {k: round(STATS[k] / max(1, STATS["solves"]), 2) for k in ("iterations", "refinements", "reorth")}
     dt = t1 - t0
     value = total / dt
-
-    # dominant kernel class by time
-    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
-    roofline = roofline_of(dom_name, dom)
-    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None,
-                   "TFLOPs": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] > 0 and v["flops"] else None}
-               for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    # roofline of the dominant class from its launches in the timed steps
+    roofline = roofline_of(dom_name, prof[dom_name])
+    rec = counted_traffic(dom_name)
+    if rec is not None:
+        roofline["traffic"] = rec["traffic_bytes_per_dispatch"]
+        roofline["traffic_algorithmic"] = rec["algorithmic_bytes_per_dispatch"]
+        roofline["traffic_launch"] = rec["launch"]
 
     # plain FP64 GPU solve of the same workload
-    opts64 = gsm.default_opts(tol=TOL, precision=gsm.GSM_FP64, restart=30)
-    run_step(gsm, work, opts64)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    n64 = 0
-    for _ in range(args.fp64_steps):
-        n, _ = run_step(gsm, work, opts64)
-        n64 += n
-    torch.cuda.synchronize()
-    fp64_value = n64 / (time.perf_counter() - t2)
+    fp64 = None
+    if args.fp64_steps > 0:
+        opts64 = gsm.default_opts(tol=TOL, precision=gsm.GSM_FP64, restart=30)
+        run_step(gsm, work, opts64)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        n64 = 0
+        for _ in range(args.fp64_steps):
+            n, _ = run_step(gsm, work, opts64)
+            n64 += n
+        torch.cuda.synchronize()
+        fp64 = {"value": round(n64 / (time.perf_counter() - t2), 3), "unit": "solves/s"}
 
     # the literal 4-solve case: x, y drives at normal incidence, both bodies
-    small = build_workload(gsm, inputs, 0)
-    run_step(gsm, small, opts)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    ns = 0
-    for _ in range(args.config_steps):
-        n, _ = run_step(gsm, small, opts)
-        ns += n
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    as_configured = {"value": round(ns / (t4 - t3), 3), "unit": "solves/s", "solves_per_step": ns // args.config_steps,
-                     "ms_per_step": round((t4 - t3) / args.config_steps * 1e3, 3)}
+    as_configured = None
+    if args.config_steps > 0:
+        small = build_workload(gsm, inputs, 0)
+        run_step(gsm, small, opts)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        ns = 0
+        for _ in range(args.config_steps):
+            n, _ = run_step(gsm, small, opts)
+            ns += n
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        as_configured = {"value": round(ns / (t4 - t3), 3), "unit": "solves/s",
+                         "solves_per_step": ns // args.config_steps,
+                         "ms_per_step": round((t4 - t3) / args.config_steps * 1e3, 3)}
 
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     per_step = total // args.steps
@@ -272,7 +319,7 @@ def main():
                    "solves_per_step": per_step, "max_rel_residual": worst,
                    "per_solve_mean": krylov},
         "roofline": roofline,
-        "fp64_gpu_solve": {"value": round(fp64_value, 3), "unit": "solves/s"},
+        "fp64_gpu_solve": fp64,
         "as_configured": as_configured,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -251,6 +251,11 @@ typedef struct gsm_kernel_stat {
 
 /* Start collecting (clears earlier records).  Not thread-safe. */
 int gsm_profile_begin(void);
+/* The same, recording only the launches of one kernel class, given by its
+ * name without the precision suffix (e.g. "pass_b"), so that a timed run
+ * carries one event pair per launch of that class only.  GSM_E_ARG for an
+ * unknown name. */
+int gsm_profile_begin_only(const char* kernel_class);
 /* Stop, synchronise the device, write up to `max` entries to out and the
  * number of classes seen to *n_out. */
 int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out);

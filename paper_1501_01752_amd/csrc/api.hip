@@ -512,6 +512,7 @@ struct ProfRec {
 
 struct Profiler {
   bool on = false;
+  int only = -1;  // record only this base class (-1: all)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -530,13 +531,27 @@ hipEvent_t prof_event() {
 template <class F>
 hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f,
                  double flops = 0.0, double funit = 0.0) {
-  if (!g_prof.on) return f();
+  if (!g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f();
   ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag,
             flops, funit};
   if (r.a) hipEventRecord(r.a, st);
   const hipError_t e = f();
   if (r.b) hipEventRecord(r.b, st);
   if (r.a && r.b) g_prof.recs.push_back(r);
+  return e;
+}
+
+// The same for launchers that take the event pair themselves (the pass
+// kernels: extended launches stamped by the dispatch packet).
+template <class F>
+hipError_t timed_ext(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f, double flops,
+                     double funit) {
+  if (!g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f(nullptr, nullptr);
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag,
+            flops, funit};
+  if (!r.a || !r.b) return f(nullptr, nullptr);
+  const hipError_t e = f(r.a, r.b);
+  g_prof.recs.push_back(r);
   return e;
 }
 
@@ -603,12 +618,20 @@ int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step
   // the contrast grid is shared by the systems of a launch: counted once
   const double grid = (double)a.g.P * a.g.P * a.g.P * sizeof(T);
   const double nb_b = step >= 0 ? 0.0 : nwork * (pb.b - grid) + grid;
-  HIP_TRY(timed(K_PASS_A, dbl, step >= 0 ? 0.0 : nwork * pb.a, step, pb.a, st, [&] { return launch_pass_a<T>(aa, st); },
-                nf * pf.a, pf.a));
-  HIP_TRY(timed(K_PASS_B, dbl, nb_b, step, pb.b - grid + grid / std::max(1, a.g.S), st,
-                [&] { return launch_pass_b<T>(a, st); }, nf * pf.b, pf.b));
-  HIP_TRY(timed(K_PASS_C, dbl, step >= 0 ? 0.0 : nwork * pb.c, step, pb.c, st, [&] { return launch_pass_c<T>(a, st); },
-                nf * pf.c, pf.c));
+  auto with_ev = [](PassArgs<T> q, hipEvent_t e0, hipEvent_t e1) {
+    q.ev0 = e0;
+    q.ev1 = e1;
+    return q;
+  };
+  HIP_TRY(timed_ext(K_PASS_A, dbl, step >= 0 ? 0.0 : nwork * pb.a, step, pb.a, st,
+                    [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_a<T>(with_ev(aa, e0, e1), st); },
+                    nf * pf.a, pf.a));
+  HIP_TRY(timed_ext(K_PASS_B, dbl, nb_b, step, pb.b - grid + grid / std::max(1, a.g.S), st,
+                    [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_b<T>(with_ev(a, e0, e1), st); },
+                    nf * pf.b, pf.b));
+  HIP_TRY(timed_ext(K_PASS_C, dbl, step >= 0 ? 0.0 : nwork * pb.c, step, pb.c, st,
+                    [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_c<T>(with_ev(a, e0, e1), st); },
+                    nf * pf.c, pf.c));
   return GSM_OK;
 }
 
@@ -704,8 +727,13 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
   int n_outer = S;  // systems still refining (known at each synchronisation)
   const double vecb = (double)n * vb;
   for (int outer = 0; outer < cap; ++outer) {
-    rc = apply_passes<double>(r, r_pa, st, n_outer);
-    if (rc) return rc;
+    if (outer == 0 && !so->x0) {
+      // x = 0: the residual is the right-hand side, no operator application
+      HIP_TRY(launch_zero_start(r.g, g.par, g.r64, adjoint ? g.rhs64 : nullptr, g.partc, st));
+    } else {
+      rc = apply_passes<double>(r, r_pa, st, n_outer);
+      if (rc) return rc;
+    }
     HIP_TRY(timed(K_FINAL, true, 0.0, -1, 0.0, st, [&] { return launch_resid_finalize(k64, fp64 ? 1 : 0, g.flags, st); }));
     HIP_TRY(hipMemcpyAsync(plan->h_flags, g.flags, 2 * S * sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1197,8 +1225,17 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
   return worst;
 }
 
-int gsm_profile_begin(void) {
+int gsm_profile_begin(void) { return gsm_profile_begin_only(nullptr); }
+
+int gsm_profile_begin_only(const char* cls) {
+  int only = -1;
+  if (cls) {
+    for (int c = 0; c < K_NBASE; ++c)
+      if (std::strcmp(cls, kClassNames[c]) == 0) only = c;
+    if (only < 0) return fail(GSM_E_ARG, "unknown kernel class '%s'", cls);
+  }
   g_prof.on = true;
+  g_prof.only = only;
   g_prof.recs.clear();
   g_prof.used = 0;
   return GSM_OK;

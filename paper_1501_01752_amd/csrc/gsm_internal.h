@@ -103,6 +103,7 @@ struct PassArgs {
   double* partial;      // pass C residual partials [S][nblk_c]
   int mode;
   int gate;
+  hipEvent_t ev0, ev1;  // when set: stamped at the start and end of the launch
 };
 
 // ---- launchers (passes.hip) ----
@@ -160,6 +161,8 @@ hipError_t launch_adjoint_weight(const AdjInst& ai, double2* lam, hipStream_t s)
 hipError_t launch_conj_mul_acc(const double2* a, const double2* e, double2* y, long long n, hipStream_t s);
 hipError_t launch_acc_real(const double2* in, double* out, long long n, double scale, hipStream_t s);
 hipError_t launch_rhs_norm(const GroupShape& g, const double2* rhs, SysParam* par, hipStream_t s);
+hipError_t launch_zero_start(const GroupShape& g, const SysParam* par, double2* r64, const double2* rhs,
+                             double* partc, hipStream_t s);
 
 // ---- plan kernels (plan.hip) ----
 // out[o][j][i] = sum_{k<nin} in[o][k][i] * exp(sign 2 pi i ((k+koff)(j+joff) mod Q) / Q)

@@ -94,6 +94,7 @@ _SIGS = {
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(SolveInfo),
                                      C.c_void_p]),
     "gsm_profile_begin": (C.c_int, []),
+    "gsm_profile_begin_only": (C.c_int, [C.c_char_p]),
     "gsm_profile_end": (C.c_int, [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
 }
 
@@ -120,8 +121,13 @@ def _check(status, allow_warn=True):
     return status
 
 
-def profile_begin():
-    _check(lib().gsm_profile_begin())
+def profile_begin(only=None):
+    """Start per-launch timing of every kernel class, or of the class `only`
+    (a name such as "pass_b", both precisions)."""
+    if only is None:
+        _check(lib().gsm_profile_begin())
+    else:
+        _check(lib().gsm_profile_begin_only(only.encode()))
 
 
 def profile_end():
