@@ -256,6 +256,8 @@ struct Group {
   double* partn = nullptr;
   double* partc = nullptr;
   int* any_reorth = nullptr;  // [restart+1] per-step second-pass flags
+  long long* off = nullptr;   // [S] offsets of the systems in the caller's flat layout (complex values)
+  void* exp = nullptr;        // [S] per-system results read back at the end
 };
 
 struct SysExport {
@@ -339,7 +341,8 @@ void build_groups(const std::vector<SysDesc>& sys, std::vector<Group>& groups) {
       sh.P = s.P;
       sh.npencil = sh.N1[0] * sh.N1[1];
       sh.n = 3LL * sh.npencil * sh.N1[2];
-      sh.tsize = 3LL * sh.npencil * s.P;
+      sh.tstride = (sh.npencil + 63) / 64 * 64;
+      sh.tsize = 3LL * sh.tstride * s.P;
       sh.nchunk = (int)((sh.n + kGsChunk - 1) / kGsChunk);
       key2g[key] = (int)groups.size();
       groups.push_back(g);
@@ -371,6 +374,8 @@ size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c
   g.partn = (double*)take(S * g.shape.nchunk * sizeof(double));
   g.partc = (double*)take(S * nblk_c * sizeof(double));
   g.any_reorth = (int*)take((restart + 1) * sizeof(int));
+  g.off = (long long*)take(S * sizeof(long long));
+  g.exp = take(S * sizeof(SysExport));
   return off;
 }
 
@@ -455,6 +460,27 @@ int ensure_flags(gsm_plan_s* plan, int n) {
 }
 
 // ---------------------------------------------------------------- kernels --
+
+// Copies between a group's contiguous [S][n] field array and the places of
+// its systems in the caller's flat layout (offsets in complex values).
+__global__ void __launch_bounds__(256) k_move_fields(double2* grp, double2* flat, const long long* off, long long n,
+                                                     int to_flat) {
+  const int s = blockIdx.y;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double2* a = grp + (long long)s * n + i;
+  double2* b = flat + off[s] + i;
+  if (to_flat)
+    *b = *a;
+  else
+    *a = *b;
+}
+
+hipError_t move_fields(const Group& g, double2* grp, const double* flat, bool to_flat, hipStream_t st) {
+  hipLaunchKernelGGL(k_move_fields, dim3((unsigned)((g.shape.n + 255) / 256), g.shape.S), dim3(256), 0, st, grp,
+                     (double2*)flat, g.off, g.shape.n, to_flat ? 1 : 0);
+  return hipGetLastError();
+}
 
 template <typename T>
 PassArgs<T> pass_args(const Group& g, const Grid* grid) {
@@ -584,7 +610,7 @@ struct PassBytes {
   double a, b, c;
 };
 PassBytes pass_bytes(const GroupShape& g, size_t bc) {
-  const double vec = (double)g.n * bc, mid = (double)g.tsize * bc;
+  const double vec = (double)g.n * bc, mid = 3.0 * g.npencil * g.P * bc;  // padding not counted
   const double grid = (double)g.P * g.P * g.P * (bc / 2);
   return {vec + mid, 2 * mid + grid, mid + 2 * vec};
 }
@@ -690,11 +716,7 @@ int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const
   if (rc) return rc;
   g_prof.group_tag++;
   HIP_TRY(launch_state_init(g.shape, g.st, g.x64, nullptr, st));
-  if (so->x0) {
-    for (int k = 0; k < S; ++k)
-      HIP_TRY(hipMemcpyAsync(g.x64 + (long long)k * n, so->x0 + 2 * sys[g.sys[k]].out_off, n * sizeof(double2),
-                             hipMemcpyDeviceToDevice, st));
-  }
+  if (so->x0) HIP_TRY(move_fields(g, g.x64, so->x0, false, st));
   KrylovArgs<double> k64 = krylov_args<double>(g, m);
   KrylovArgs<T> kt = krylov_args<T>(g, m);
   kt.host_inner = plan->h_inner;
@@ -804,9 +826,11 @@ int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& g
   int rc = carve(groups, ws, ws_bytes, so->restart, fp64);
   if (rc) return rc;
   exp.assign(sys.size(), SysExport{});
-  SysExport* d_exp = nullptr;
-  HIP_TRY(hipMalloc(&d_exp, std::max<size_t>(1, sys.size()) * sizeof(SysExport)));
   for (auto& g : groups) {
+    SysExport* d_exp = (SysExport*)g.exp;
+    std::vector<long long> offs;
+    for (int si : g.sys) offs.push_back(sys[si].out_off);
+    HIP_TRY(hipMemcpyAsync(g.off, offs.data(), offs.size() * sizeof(long long), hipMemcpyHostToDevice, st));
     Grid* grid = nullptr;
     rc = ensure_grid(plan, g.shape.M, g.shape.P, st, &grid);
     if (rc) break;
@@ -814,21 +838,21 @@ int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& g
     for (int si : g.sys) par.push_back(sys[si].par);
     HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
     if (adjoint) {
-      for (int k = 0; k < g.shape.S; ++k) {
-        const SysDesc& s = sys[g.sys[k]];
-        HIP_TRY(hipMemcpyAsync(g.rhs64 + (long long)k * g.shape.n, rhs + 2 * s.out_off, s.n * sizeof(double2),
-                               hipMemcpyDeviceToDevice, st));
-      }
+      HIP_TRY(move_fields(g, g.rhs64, rhs, false, st));
       HIP_TRY(launch_rhs_norm(g.shape, g.rhs64, g.par, st));
     }
     HIP_TRY(hipStreamSynchronize(st));
     rc = fp64 ? run_group<double>(plan, g, sys, so, grid, st, adjoint)
               : run_group<float>(plan, g, sys, so, grid, st, adjoint);
     if (rc) break;
-    for (int k = 0; k < g.shape.S; ++k) {
-      const SysDesc& s = sys[g.sys[k]];
-      HIP_TRY(hipMemcpyAsync(E_out + 2 * s.out_off, g.x64 + (long long)k * g.shape.n, s.n * sizeof(double2),
-                             out_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    if (out_host) {
+      for (int k = 0; k < g.shape.S; ++k) {
+        const SysDesc& s = sys[g.sys[k]];
+        HIP_TRY(hipMemcpyAsync(E_out + 2 * s.out_off, g.x64 + (long long)k * g.shape.n, s.n * sizeof(double2),
+                               hipMemcpyDeviceToHost, st));
+      }
+    } else {
+      HIP_TRY(move_fields(g, g.x64, E_out, true, st));
     }
     hipLaunchKernelGGL(k_export, dim3((g.shape.S + 63) / 64), dim3(64), 0, st, g.st, g.x64, g.shape, d_exp);
     HIP_TRY(hipGetLastError());
@@ -837,7 +861,6 @@ int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& g
     HIP_TRY(hipStreamSynchronize(st));
     for (int k = 0; k < g.shape.S; ++k) exp[g.sys[k]] = ge[k];
   }
-  hipFree(d_exp);
   return rc;
 }
 

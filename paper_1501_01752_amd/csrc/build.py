@@ -1,7 +1,9 @@
 #!/usr/bin/env python3
 """Build libgsm.so for gfx950 in-tree: generate the FFT codelets, compile each
 translation unit with hipcc in parallel and link the shared library next to
-the Python package.  Usage: python build.py [--jobs N]"""
+the Python package.  Usage: python build.py [--jobs N] [--out PATH] [-D NAME=VALUE ...]
+(--out and -D build a variant library elsewhere, e.g. for comparing kernel
+settings; the package loads it when GSM_LIBRARY names it)."""
 import argparse
 import os
 import subprocess
@@ -30,18 +32,23 @@ def run(cmd):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--out", default=os.path.join(PKG, "libgsm.so"))
+    ap.add_argument("-D", dest="defines", action="append", default=[])
     args = ap.parse_args()
-    os.makedirs(BUILD, exist_ok=True)
+    build = BUILD if not args.defines else os.path.join(BUILD, "variant_" + "_".join(
+        d.replace("=", "-") for d in args.defines))
+    os.makedirs(build, exist_ok=True)
+    flags = FLAGS + ["-D" + d for d in args.defines]
     run([sys.executable, os.path.join(HERE, "gen_fft.py"), os.path.join(HERE, "fft_codelets.h")])
 
     def compile_unit(u):
-        obj = os.path.join(BUILD, u.replace(".hip", ".o"))
-        run([HIPCC] + FLAGS + ["-c", os.path.join(HERE, u), "-o", obj])
+        obj = os.path.join(build, u.replace(".hip", ".o"))
+        run([HIPCC] + flags + ["-c", os.path.join(HERE, u), "-o", obj])
         return obj
 
     with ThreadPoolExecutor(args.jobs) as ex:
         objs = list(ex.map(compile_unit, UNITS))
-    out = os.path.join(PKG, "libgsm.so")
+    out = os.path.abspath(args.out)
     tmp = out + ".tmp"
     run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, out)

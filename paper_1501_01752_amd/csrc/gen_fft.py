@@ -258,7 +258,7 @@ def codelet_specs():
     # lane runs a full length-N transform.
     for p in (4, 8, 16, 32, 64, 128):
         k = (p - 1) // 4
-        for lane_max in (32, 16):
+        for lane_max in (64, 32, 16):
             n = min(p, lane_max)
             if 2 * k + 1 <= n:
                 pairs.add((n, k))

@@ -11,7 +11,10 @@ namespace gsm {
 constexpr int kMaxRestart = 64;   // largest Krylov dimension per cycle
 constexpr int kMaxOrder = 31;     // largest M_a (P = 128)
 constexpr int kGsThreads = 256;   // block size of the Gram-Schmidt kernels
-constexpr int kGsPerThread = 8;   // vector elements per thread in those kernels
+#ifndef GSM_GS_PER_THREAD
+#define GSM_GS_PER_THREAD 8
+#endif
+constexpr int kGsPerThread = GSM_GS_PER_THREAD;  // vector elements per thread in those kernels
 constexpr int kGsChunk = kGsThreads * kGsPerThread;
 
 template <typename T> struct cplx_t;
@@ -73,8 +76,11 @@ struct GroupShape {
   int N1[3];
   int P;
   int npencil;      // N1x * N1y
+  int tstride;      // pencils per intermediate plane: npencil rounded up to 64, so the
+                    // pencil segments of pass C blocks (16-64 pencils) start on whole
+                    // cache lines and the last block's segment stays inside the plane
   long long n;      // 3 * N1x * N1y * N1z complex values per system
-  long long tsize;  // 3 * npencil * P complex values per system (intermediate)
+  long long tsize;  // 3 * tstride * P complex values per system (intermediate)
   int nchunk;       // ceil(n / kGsChunk)
   int nblk_c;       // pass C blocks per system
 };

@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgsm.so")
+LIB_PATH = os.environ.get("GSM_LIBRARY") or os.path.join(_HERE, "libgsm.so")
 
 GSM_OK, GSM_W_NOT_CONVERGED = 0, 1
 GSM_E_ARG, GSM_E_NONFINITE, GSM_E_NOMEM, GSM_E_DEVICE = -1, -2, -3, -4
