@@ -62,6 +62,20 @@ struct Grid {
 
 }  // namespace
 
+// Host-side resources of one group in flight: its stream, the events the
+// host polls, pinned words the kernels and copies write for the host.
+constexpr int kSlots = 4;  // groups of one call in flight at once
+constexpr int kRing = 8;   // step events per slot (more than the host's lead)
+struct RunSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t step_ev[kRing] = {};
+  hipEvent_t phase_ev = nullptr;  // residual check or export done
+  int* h_flags = nullptr;         // pinned [2 cap]: active flags | steps of the last cycle
+  int* h_inner = nullptr;         // pinned [cap]: cycle still running (written by kernels)
+  void* h_exp = nullptr;          // pinned [cap] per-system results
+  int cap = 0;
+};
+
 struct gsm_plan_s {
   int device = 0;
   double period[3]{};
@@ -71,10 +85,7 @@ struct gsm_plan_s {
   double eps_mean = 0, eps_min = 0, eps_max = 0;
   double2* d_coef = nullptr;
   std::map<std::array<int, 4>, Grid> grids;
-  int* h_flags = nullptr;  // pinned
-  int* h_inner = nullptr;  // pinned, written by the Givens kernel
-  int h_flags_cap = 0;
-  hipEvent_t step_ev[gsm::kMaxRestart] = {};
+  RunSlot slots[kSlots];
 };
 
 namespace {
@@ -445,17 +456,25 @@ int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** 
   return GSM_OK;
 }
 
-int ensure_flags(gsm_plan_s* plan, int n) {
-  if (!plan->step_ev[0])
-    for (int j = 0; j < kMaxRestart; ++j) HIP_TRY(hipEventCreateWithFlags(&plan->step_ev[j], hipEventDisableTiming));
-  if (plan->h_flags_cap >= n) return GSM_OK;
-  if (plan->h_flags) HIP_TRY(hipHostFree(plan->h_flags));
-  if (plan->h_inner) HIP_TRY(hipHostFree(plan->h_inner));
-  plan->h_flags = plan->h_inner = nullptr;
-  const int cap = std::max(n, 64);
-  HIP_TRY(hipHostMalloc((void**)&plan->h_flags, cap * sizeof(int), hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc((void**)&plan->h_inner, cap * sizeof(int), hipHostMallocDefault));
-  plan->h_flags_cap = cap;
+int ensure_slot(gsm_plan_s* plan, int k, int S, size_t exp_bytes) {
+  RunSlot& sl = plan->slots[k];
+  if (!sl.stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+    for (int j = 0; j < kRing; ++j) HIP_TRY(hipEventCreateWithFlags(&sl.step_ev[j], hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&sl.phase_ev, hipEventDisableTiming));
+  }
+  if (sl.cap >= S) return GSM_OK;
+  if (sl.h_flags) HIP_TRY(hipHostFree(sl.h_flags));
+  if (sl.h_inner) HIP_TRY(hipHostFree(sl.h_inner));
+  if (sl.h_exp) HIP_TRY(hipHostFree(sl.h_exp));
+  sl.h_flags = sl.h_inner = nullptr;
+  sl.h_exp = nullptr;
+  sl.cap = 0;
+  const int cap = std::max(S, 64);
+  HIP_TRY(hipHostMalloc((void**)&sl.h_flags, 2 * cap * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc((void**)&sl.h_inner, cap * sizeof(int), hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(&sl.h_exp, cap * exp_bytes, hipHostMallocDefault));
+  sl.cap = cap;
   return GSM_OK;
 }
 
@@ -542,7 +561,8 @@ struct Profiler {
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  int group_tag = 0;
+  int group_tag = 0;    // tag of the group whose work is being issued
+  int tag_counter = 0;  // source of group tags
 } g_prof;
 
 hipEvent_t prof_event() {
@@ -661,144 +681,10 @@ int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step
   return GSM_OK;
 }
 
-constexpr int kLead = 2;  // Arnoldi steps the host may run ahead of the device
-
-// One BiCGStab cycle of a group (A d = r / rho from d = 0, x += rho d in
-// FP64 as it goes), issued like the Arnoldi steps: at most kLead iterations
-// ahead of the device, ending when every system's cycle has ended.
-template <typename T>
-int bicg_cycle(gsm_plan_s* plan, const KrylovArgs<T>& kt, PassArgs<T> pa, int r_pa, cplx<T>* V, int S,
-               long long n, const gsm_solver_opts* so, hipStream_t st) {
-  const bool fp64 = sizeof(T) == 8;
-  const double vecb = (double)n * sizeof(cplx<T>);
-  const int cap = std::max(1, so->max_iter / 2 + 1);
-  int n_act = 0;
-  for (int s = 0; s < S; ++s) n_act += plan->h_flags[s] != 0;
-  HIP_TRY(timed(K_BICG_INIT, fp64, n_act * (n * sizeof(double2) + 3 * vecb), -1, 0.0, st,
-                [&] { return launch_bicg<T>(kt, BICG_INIT, 0, cap, st); }));
-  for (int it = 0; it < cap; ++it) {
-    pa.x = V + BI_P * n;
-    pa.y = V + BI_V * n;
-    int rc = apply_passes<T>(pa, r_pa, st, 0, it);
-    if (rc) return rc;
-    HIP_TRY(timed(K_BICG_DOT, fp64, 0.0, it, 2 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_DOT_RV, it, cap, st); }));
-    HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 3 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_S, it, cap, st); }));
-    pa.x = V + BI_S * n;
-    pa.y = V + BI_T * n;
-    rc = apply_passes<T>(pa, r_pa, st, 0, it);
-    if (rc) return rc;
-    HIP_TRY(timed(K_BICG_DOT, fp64, 0.0, it, 2 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_DOT_TS, it, cap, st); }));
-    HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 5 * vecb + 2.0 * n * sizeof(double2), st,
-                  [&] { return launch_bicg<T>(kt, BICG_XR, it, cap, st); }));
-    HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 4 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_P, it, cap, st); }));
-    HIP_TRY(hipEventRecord(plan->step_ev[it % kMaxRestart], st));
-    if (it >= kLead) {
-      HIP_TRY(hipEventSynchronize(plan->step_ev[(it - kLead) % kMaxRestart]));
-      bool running = false;
-      for (int s = 0; s < S && !running; ++s) running = plan->h_inner[s] != 0;
-      if (!running) break;
-    }
-  }
-  HIP_TRY(launch_bicg<T>(kt, BICG_END, 0, cap, st));
-  return GSM_OK;
-}
-
-// The solve loop of one group.
-template <typename T>
-int run_group(gsm_plan_s* plan, Group& g, const std::vector<SysDesc>& sys, const gsm_solver_opts* so,
-              const Grid* grid, hipStream_t st, bool adjoint) {
-  const int S = g.shape.S;
-  const long long n = g.shape.n;
-  const int m = so->restart;
-  const bool fp64 = sizeof(T) == 8;
-  const size_t vb = sizeof(cplx<T>);
-  int rc = ensure_flags(plan, 2 * S);
-  if (rc) return rc;
-  g_prof.group_tag++;
-  HIP_TRY(launch_state_init(g.shape, g.st, g.x64, nullptr, st));
-  if (so->x0) HIP_TRY(move_fields(g, g.x64, so->x0, false, st));
-  KrylovArgs<double> k64 = krylov_args<double>(g, m);
-  KrylovArgs<T> kt = krylov_args<T>(g, m);
-  kt.host_inner = plan->h_inner;
-  PassArgs<double> r = pass_args<double>(g, grid);
-  r.g.nblk_c = nblk_c_for(g.shape, true);
-  k64.g.nblk_c = r.g.nblk_c;
-  r.x = g.x64;
-  r.xs = n;
-  r.y = g.r64;
-  r.ys = n;
-  // forward: A = I - B with B = G V; adjoint: A^H = I - B^H with B^H = V G
-  // (G real symmetric, V Hermitian for real eps), i.e. the Green tensor is
-  // applied by pass A before the convolution
-  r.mode = adjoint ? PC_ADJ_RESID : PC_RESID;
-  r.rhs = g.rhs64;
-  r.rs = n;
-  r.gate = GATE_OUTER;
-  const int r_pa = adjoint ? PA_GREEN_PRE : 0;
-  PassArgs<T> p = pass_args<T>(g, grid);
-  p.g.nblk_c = nblk_c_for(g.shape, fp64);
-  p.xs = (long long)(m + 1) * n;
-  p.ys = p.xs;
-  p.mode = adjoint ? PC_CONV : PC_GREEN;  // the Arnoldi process runs on B (or B^H)
-  p.gate = GATE_INNER;
-  PassArgs<T> pbi = p;                    // BiCGStab applies A (or A^H) itself
-  pbi.mode = adjoint ? PC_ADJ : PC_FWD;
-  const bool bicg = so->method == GSM_BICGSTAB;
-  cplx<T>* V = (cplx<T>*)g.V;
-  const int cap = so->max_refine + 2;
-  int n_outer = S;  // systems still refining (known at each synchronisation)
-  const double vecb = (double)n * vb;
-  for (int outer = 0; outer < cap; ++outer) {
-    if (outer == 0 && !so->x0) {
-      // x = 0: the residual is the right-hand side, no operator application
-      HIP_TRY(launch_zero_start(r.g, g.par, g.r64, adjoint ? g.rhs64 : nullptr, g.partc, st));
-    } else {
-      rc = apply_passes<double>(r, r_pa, st, n_outer);
-      if (rc) return rc;
-    }
-    HIP_TRY(timed(K_FINAL, true, 0.0, -1, 0.0, st, [&] { return launch_resid_finalize(k64, fp64 ? 1 : 0, g.flags, st); }));
-    HIP_TRY(hipMemcpyAsync(plan->h_flags, g.flags, 2 * S * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    prof_resolve(plan->h_flags + S, S, n, vb);
-    n_outer = 0;
-    for (int s = 0; s < S; ++s) n_outer += plan->h_flags[s] != 0;
-    if (!n_outer) break;
-    if (bicg) {
-      rc = bicg_cycle<T>(plan, kt, pbi, r_pa, V, S, n, so, st);
-      if (rc) return rc;
-      continue;
-    }
-    HIP_TRY(timed(K_CAST, fp64, n_outer * (n * sizeof(double2) + vecb), -1, 0.0, st,
-                  [&] { return launch_cast_v0<T>(kt, st); }));
-    // Issue the Arnoldi steps of one cycle, staying at most kLead steps ahead
-    // of the device: after step j the host waits for step j - kLead and
-    // stops as soon as every system's cycle has ended (the Givens kernel
-    // writes the per-system flags to pinned host memory).
-    for (int j = 0; j < m; ++j) {
-      p.x = V + (long long)j * n;
-      p.y = V + (long long)(j + 1) * n;
-      rc = apply_passes<T>(p, r_pa | (j > 0 ? PA_NORMALIZE : 0), st, 0, j);
-      if (rc) return rc;
-      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, st); }));
-      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, st); }));
-      // finish: Givens step, unless the first pass removed nearly all of w;
-      // those systems get a second Gram-Schmidt pass, whose kernels return
-      // at once when no system of the group asked for one (its bytes are
-      // not attributed: the host does not know how often it runs)
-      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, st); }));
-      HIP_TRY(timed(K_CGS_RE, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_second_pass<T>(kt, j, st); }));
-      HIP_TRY(hipEventRecord(plan->step_ev[j], st));
-      if (j >= kLead) {
-        HIP_TRY(hipEventSynchronize(plan->step_ev[j - kLead]));
-        bool running = false;
-        for (int s = 0; s < S && !running; ++s) running = plan->h_inner[s] != 0;
-        if (!running) break;
-      }
-    }
-    HIP_TRY(timed(K_LSQ, fp64, 0.0, -2, 0.0, st, [&] { return launch_lsq_update<T>(kt, st); }));
-  }
-  return GSM_OK;
-}
+#ifndef GSM_LEAD
+#define GSM_LEAD 2
+#endif
+constexpr int kLead = GSM_LEAD;  // Arnoldi steps the host may run ahead of the device
 
 __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, SysExport* out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -818,50 +704,348 @@ __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, S
   out[s] = e;
 }
 
+// The solve of one group as a state machine the scheduler advances without
+// blocking: FP64 residual check -> Krylov cycle (Arnoldi steps or BiCGStab
+// iterations issued at most kLead ahead of the device; the host stops when
+// the kernels' pinned per-system flags say every cycle has ended) -> residual
+// check ... -> export of the results.  Everything runs on the slot's stream.
+template <typename T>
+struct GroupRun {
+  enum Phase { START, RESID_WAIT, CYCLE, EXPORT_WAIT, DONE };
+  gsm_plan_s* plan = nullptr;
+  Group* g = nullptr;
+  RunSlot* sl = nullptr;
+  const gsm_solver_opts* so = nullptr;
+  const std::vector<SysDesc>* sys = nullptr;
+  const double* rhs = nullptr;  // adjoint right-hand sides (flat layout) or null
+  double* E_out = nullptr;
+  bool out_host = false;
+  std::vector<SysExport>* exp = nullptr;
+  int tag = 0;
+  hipStream_t st = nullptr;
+
+  KrylovArgs<double> k64{};
+  KrylovArgs<T> kt{};
+  PassArgs<double> r{};
+  PassArgs<T> p{}, pbi{};
+  int r_pa = 0, S = 0, m = 0, cap_outer = 0, it_cap = 0;
+  long long n = 0;
+  bool adjoint = false, bicg = false;
+  static constexpr bool fp64 = sizeof(T) == 8;
+  static constexpr size_t vb = sizeof(cplx<T>);
+  double vecb = 0;
+  cplx<T>* V = nullptr;
+  std::vector<SysParam> par_host;
+  std::vector<long long> off_host;
+
+  Phase phase = START;
+  int outer = 0, j = 0, n_outer = 0;
+
+  void setup(const Grid* grid) {
+    S = g->shape.S;
+    n = g->shape.n;
+    m = so->restart;
+    adjoint = rhs != nullptr;
+    bicg = so->method == GSM_BICGSTAB;
+    vecb = (double)n * vb;
+    st = sl->stream;
+    k64 = krylov_args<double>(*g, m);
+    kt = krylov_args<T>(*g, m);
+    kt.host_inner = sl->h_inner;
+    r = pass_args<double>(*g, grid);
+    r.g.nblk_c = nblk_c_for(g->shape, true);
+    k64.g.nblk_c = r.g.nblk_c;
+    r.x = g->x64;
+    r.xs = n;
+    r.y = g->r64;
+    r.ys = n;
+    // forward: A = I - B with B = G V; adjoint: A^H = I - B^H with B^H = V G
+    // (G real symmetric, V Hermitian for real eps), i.e. the Green tensor is
+    // applied by pass A before the convolution
+    r.mode = adjoint ? PC_ADJ_RESID : PC_RESID;
+    r.rhs = g->rhs64;
+    r.rs = n;
+    r.gate = GATE_OUTER;
+    r_pa = adjoint ? PA_GREEN_PRE : 0;
+    p = pass_args<T>(*g, grid);
+    p.g.nblk_c = nblk_c_for(g->shape, fp64);
+    p.xs = (long long)(m + 1) * n;
+    p.ys = p.xs;
+    p.mode = adjoint ? PC_CONV : PC_GREEN;  // the Arnoldi process runs on B (or B^H)
+    p.gate = GATE_INNER;
+    pbi = p;                                // BiCGStab applies A (or A^H) itself
+    pbi.mode = adjoint ? PC_ADJ : PC_FWD;
+    V = (cplx<T>*)g->V;
+    cap_outer = so->max_refine + 2;
+    it_cap = std::max(1, so->max_iter / 2 + 1);
+    for (int si : g->sys) {
+      par_host.push_back((*sys)[si].par);
+      off_host.push_back((*sys)[si].out_off);
+    }
+  }
+
+  int issue_residual() {
+    if (outer == 0 && !so->x0) {
+      // x = 0: the residual is the right-hand side, no operator application
+      HIP_TRY(launch_zero_start(r.g, g->par, g->r64, adjoint ? g->rhs64 : nullptr, g->partc, st));
+    } else {
+      const int rc = apply_passes<double>(r, r_pa, st, n_outer);
+      if (rc) return rc;
+    }
+    ++outer;
+    HIP_TRY(timed(K_FINAL, true, 0.0, -1, 0.0, st, [&] { return launch_resid_finalize(k64, fp64 ? 1 : 0, g->flags, st); }));
+    HIP_TRY(hipMemcpyAsync(sl->h_flags, g->flags, 2 * S * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(sl->phase_ev, st));
+    phase = RESID_WAIT;
+    return GSM_OK;
+  }
+
+  int issue_export() {
+    if (out_host) {
+      for (int k = 0; k < S; ++k) {
+        const SysDesc& d = (*sys)[g->sys[k]];
+        HIP_TRY(hipMemcpyAsync(E_out + 2 * d.out_off, g->x64 + (long long)k * n, d.n * sizeof(double2),
+                               hipMemcpyDeviceToHost, st));
+      }
+    } else {
+      HIP_TRY(move_fields(*g, g->x64, E_out, true, st));
+    }
+    hipLaunchKernelGGL(k_export, dim3((S + 63) / 64), dim3(64), 0, st, g->st, g->x64, g->shape, (SysExport*)g->exp);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(sl->h_exp, g->exp, S * sizeof(SysExport), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(sl->phase_ev, st));
+    phase = EXPORT_WAIT;
+    return GSM_OK;
+  }
+
+  int issue_step() {
+    if (bicg) {
+      const int it = j;
+      pbi.x = V + BI_P * n;
+      pbi.y = V + BI_V * n;
+      int rc = apply_passes<T>(pbi, r_pa, st, 0, it);
+      if (rc) return rc;
+      HIP_TRY(timed(K_BICG_DOT, fp64, 0.0, it, 2 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_DOT_RV, it, it_cap, st); }));
+      HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 3 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_S, it, it_cap, st); }));
+      pbi.x = V + BI_S * n;
+      pbi.y = V + BI_T * n;
+      rc = apply_passes<T>(pbi, r_pa, st, 0, it);
+      if (rc) return rc;
+      HIP_TRY(timed(K_BICG_DOT, fp64, 0.0, it, 2 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_DOT_TS, it, it_cap, st); }));
+      HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 5 * vecb + 2.0 * n * sizeof(double2), st,
+                    [&] { return launch_bicg<T>(kt, BICG_XR, it, it_cap, st); }));
+      HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 4 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_P, it, it_cap, st); }));
+    } else {
+      p.x = V + (long long)j * n;
+      p.y = V + (long long)(j + 1) * n;
+      const int rc = apply_passes<T>(p, r_pa | (j > 0 ? PA_NORMALIZE : 0), st, 0, j);
+      if (rc) return rc;
+      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, st); }));
+      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, st); }));
+      // finish: Givens step, unless the first pass removed nearly all of w;
+      // those systems get a second Gram-Schmidt pass, whose kernels return
+      // at once when no system of the group asked for one (its bytes are
+      // not attributed: the host does not know how often it runs)
+      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, st); }));
+      HIP_TRY(timed(K_CGS_RE, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_second_pass<T>(kt, j, st); }));
+    }
+    HIP_TRY(hipEventRecord(sl->step_ev[j % kRing], st));
+    ++j;
+    return GSM_OK;
+  }
+
+  int end_cycle() {
+    if (bicg)
+      HIP_TRY(launch_bicg<T>(kt, BICG_END, 0, it_cap, st));
+    else
+      HIP_TRY(timed(K_LSQ, fp64, 0.0, -2, 0.0, st, [&] { return launch_lsq_update<T>(kt, st); }));
+    return issue_residual();
+  }
+
+  // Issue everything that needs no wait; *moved says whether anything was.
+  int advance(bool* moved) {
+    *moved = false;
+    g_prof.group_tag = tag;
+    int rc = GSM_OK;
+    switch (phase) {
+      case START:
+        HIP_TRY(hipMemcpyAsync(g->par, par_host.data(), S * sizeof(SysParam), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(g->off, off_host.data(), S * sizeof(long long), hipMemcpyHostToDevice, st));
+        if (adjoint) {
+          HIP_TRY(move_fields(*g, g->rhs64, rhs, false, st));
+          HIP_TRY(launch_rhs_norm(g->shape, g->rhs64, g->par, st));
+        }
+        HIP_TRY(launch_state_init(g->shape, g->st, g->x64, nullptr, st));
+        if (so->x0) HIP_TRY(move_fields(*g, g->x64, so->x0, false, st));
+        n_outer = S;
+        *moved = true;
+        return issue_residual();
+      case RESID_WAIT: {
+        const hipError_t q = hipEventQuery(sl->phase_ev);
+        if (q == hipErrorNotReady) return GSM_OK;
+        HIP_TRY(q);
+        *moved = true;
+        prof_resolve(sl->h_flags + S, S, n, vb);
+        n_outer = 0;
+        for (int s = 0; s < S; ++s) n_outer += sl->h_flags[s] != 0;
+        if (!n_outer || outer >= cap_outer) return issue_export();
+        j = 0;
+        phase = CYCLE;
+        if (bicg) {
+          HIP_TRY(timed(K_BICG_INIT, fp64, n_outer * (n * sizeof(double2) + 3 * vecb), -1, 0.0, st,
+                        [&] { return launch_bicg<T>(kt, BICG_INIT, 0, it_cap, st); }));
+        } else {
+          HIP_TRY(timed(K_CAST, fp64, n_outer * (n * sizeof(double2) + vecb), -1, 0.0, st,
+                        [&] { return launch_cast_v0<T>(kt, st); }));
+        }
+        return GSM_OK;
+      }
+      case CYCLE:
+        for (;;) {
+          const int limit = bicg ? it_cap : m;
+          if (j >= limit) {
+            *moved = true;
+            return end_cycle();
+          }
+          if (j >= kLead) {
+            const hipError_t q = hipEventQuery(sl->step_ev[(j - kLead) % kRing]);
+            if (q == hipErrorNotReady) return GSM_OK;
+            HIP_TRY(q);
+            bool running = false;
+            for (int s = 0; s < S && !running; ++s) running = sl->h_inner[s] != 0;
+            if (!running) {
+              *moved = true;
+              return end_cycle();
+            }
+          }
+          if ((rc = issue_step())) return rc;
+          *moved = true;
+        }
+      case EXPORT_WAIT: {
+        const hipError_t q = hipEventQuery(sl->phase_ev);
+        if (q == hipErrorNotReady) return GSM_OK;
+        HIP_TRY(q);
+        const SysExport* e = (const SysExport*)sl->h_exp;
+        for (int k = 0; k < S; ++k) (*exp)[g->sys[k]] = e[k];
+        phase = DONE;
+        *moved = true;
+        return GSM_OK;
+      }
+      case DONE:
+        return GSM_OK;
+    }
+    return GSM_OK;
+  }
+
+  // the event a blocked run waits on
+  hipEvent_t blocker() const {
+    if (phase == CYCLE) return sl->step_ev[(j - kLead + kRing) % kRing];
+    return sl->phase_ev;
+  }
+};
+
+// Run every group of a call: the largest groups first, up to kSlots at once,
+// each on a stream of its own, their steps interleaved by the host (a work
+// queue: a slot takes the next group as soon as its group is done).  The
+// slots' streams start after the work queued on the caller's stream and the
+// caller's stream waits for them at the end.
+template <typename T>
+int run_groups(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& groups,
+               std::vector<const Grid*>& grids, const gsm_solver_opts* so, double* E_out, bool out_host,
+               std::vector<SysExport>& exp, hipStream_t st, const double* rhs) {
+  std::vector<int> order(groups.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (double)groups[a].shape.S * groups[a].shape.tsize > (double)groups[b].shape.S * groups[b].shape.tsize;
+  });
+  int max_s = 0;
+  for (auto& g : groups) max_s = std::max(max_s, g.shape.S);
+  const int nslot = std::min<int>(kSlots, (int)groups.size());
+  hipEvent_t start = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  int rc = GSM_OK;
+  auto finish = [&](int code) {
+    for (int k = 0; k < nslot; ++k) {
+      RunSlot& sl = plan->slots[k];
+      if (!sl.stream) continue;
+      if (code) hipStreamSynchronize(sl.stream);
+      if (hipEventRecord(sl.phase_ev, sl.stream) == hipSuccess) (void)hipStreamWaitEvent(st, sl.phase_ev, 0);
+    }
+    (void)hipEventDestroy(start);
+    return code;
+  };
+  HIP_TRY(hipEventRecord(start, st));
+  for (int k = 0; k < nslot; ++k) {
+    if ((rc = ensure_slot(plan, k, max_s, sizeof(SysExport)))) return finish(rc);
+    if (hipStreamWaitEvent(plan->slots[k].stream, start, 0) != hipSuccess)
+      return finish(fail(GSM_E_DEVICE, "stream wait failed"));
+  }
+  std::vector<GroupRun<T>> runs(groups.size());
+  std::vector<int> active(nslot, -1);
+  size_t next = 0;
+  int done = 0;
+  while (done < (int)groups.size()) {
+    for (int k = 0; k < nslot; ++k) {
+      if (active[k] >= 0 || next >= order.size()) continue;
+      const int gi = order[next++];
+      GroupRun<T>& R = runs[gi];
+      R.plan = plan;
+      R.g = &groups[gi];
+      R.sl = &plan->slots[k];
+      R.so = so;
+      R.sys = &sys;
+      R.rhs = rhs;
+      R.E_out = E_out;
+      R.out_host = out_host;
+      R.exp = &exp;
+      R.tag = ++g_prof.tag_counter;
+      R.setup(grids[gi]);
+      active[k] = gi;
+    }
+    bool any = false;
+    for (int k = 0; k < nslot; ++k) {
+      if (active[k] < 0) continue;
+      GroupRun<T>& R = runs[active[k]];
+      bool moved = false;
+      if ((rc = R.advance(&moved))) return finish(rc);
+      any = any || moved;
+      if (R.phase == GroupRun<T>::DONE) {
+        active[k] = -1;
+        ++done;
+        any = true;
+      }
+    }
+    if (!any) {
+      // nothing can be issued: sleep on what the first active group waits for
+      for (int k = 0; k < nslot; ++k)
+        if (active[k] >= 0) {
+          const hipError_t e = hipEventSynchronize(runs[active[k]].blocker());
+          if (e != hipSuccess) return finish(fail(GSM_E_DEVICE, "%s", hipGetErrorString(e)));
+          break;
+        }
+    }
+  }
+  return finish(GSM_OK);
+}
+
 int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& groups, const gsm_solver_opts* so,
               void* ws, size_t ws_bytes, double* E_out, bool out_host, std::vector<SysExport>& exp,
               hipStream_t st, const double* rhs = nullptr) {
   const bool fp64 = so->precision == GSM_FP64;
-  const bool adjoint = rhs != nullptr;
   int rc = carve(groups, ws, ws_bytes, so->restart, fp64);
   if (rc) return rc;
   exp.assign(sys.size(), SysExport{});
-  for (auto& g : groups) {
-    SysExport* d_exp = (SysExport*)g.exp;
-    std::vector<long long> offs;
-    for (int si : g.sys) offs.push_back(sys[si].out_off);
-    HIP_TRY(hipMemcpyAsync(g.off, offs.data(), offs.size() * sizeof(long long), hipMemcpyHostToDevice, st));
+  std::vector<const Grid*> grids(groups.size());
+  for (size_t i = 0; i < groups.size(); ++i) {
     Grid* grid = nullptr;
-    rc = ensure_grid(plan, g.shape.M, g.shape.P, st, &grid);
-    if (rc) break;
-    std::vector<SysParam> par;
-    for (int si : g.sys) par.push_back(sys[si].par);
-    HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
-    if (adjoint) {
-      HIP_TRY(move_fields(g, g.rhs64, rhs, false, st));
-      HIP_TRY(launch_rhs_norm(g.shape, g.rhs64, g.par, st));
-    }
-    HIP_TRY(hipStreamSynchronize(st));
-    rc = fp64 ? run_group<double>(plan, g, sys, so, grid, st, adjoint)
-              : run_group<float>(plan, g, sys, so, grid, st, adjoint);
-    if (rc) break;
-    if (out_host) {
-      for (int k = 0; k < g.shape.S; ++k) {
-        const SysDesc& s = sys[g.sys[k]];
-        HIP_TRY(hipMemcpyAsync(E_out + 2 * s.out_off, g.x64 + (long long)k * g.shape.n, s.n * sizeof(double2),
-                               hipMemcpyDeviceToHost, st));
-      }
-    } else {
-      HIP_TRY(move_fields(g, g.x64, E_out, true, st));
-    }
-    hipLaunchKernelGGL(k_export, dim3((g.shape.S + 63) / 64), dim3(64), 0, st, g.st, g.x64, g.shape, d_exp);
-    HIP_TRY(hipGetLastError());
-    std::vector<SysExport> ge(g.shape.S);
-    HIP_TRY(hipMemcpyAsync(ge.data(), d_exp, g.shape.S * sizeof(SysExport), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int k = 0; k < g.shape.S; ++k) exp[g.sys[k]] = ge[k];
+    if ((rc = ensure_grid(plan, groups[i].shape.M, groups[i].shape.P, st, &grid))) return rc;
+    grids[i] = grid;
   }
-  return rc;
+  rc = fp64 ? run_groups<double>(plan, sys, groups, grids, so, E_out, out_host, exp, st, rhs)
+            : run_groups<float>(plan, sys, groups, grids, so, E_out, out_host, exp, st, rhs);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(st));
+  return GSM_OK;
 }
 
 void fill_info(const std::vector<SysDesc>& sys, const std::vector<SysExport>& exp, gsm_solve_info* info,
@@ -1040,10 +1224,16 @@ int gsm_plan_destroy(gsm_plan_t p) {
     hipFree(kv.second.g32);
   }
   hipFree(p->d_coef);
-  if (p->h_flags) hipHostFree(p->h_flags);
-  if (p->h_inner) hipHostFree(p->h_inner);
-  for (int j = 0; j < kMaxRestart; ++j)
-    if (p->step_ev[j]) hipEventDestroy(p->step_ev[j]);
+  for (auto& sl : p->slots) {
+    if (sl.stream) hipStreamSynchronize(sl.stream);
+    if (sl.h_flags) hipHostFree(sl.h_flags);
+    if (sl.h_inner) hipHostFree(sl.h_inner);
+    if (sl.h_exp) hipHostFree(sl.h_exp);
+    for (auto& e : sl.step_ev)
+      if (e) hipEventDestroy(e);
+    if (sl.phase_ev) hipEventDestroy(sl.phase_ev);
+    if (sl.stream) hipStreamDestroy(sl.stream);
+  }
   delete p;
   return GSM_OK;
 }
