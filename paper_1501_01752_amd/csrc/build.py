@@ -39,7 +39,14 @@ def main():
         d.replace("=", "-") for d in args.defines))
     os.makedirs(build, exist_ok=True)
     flags = FLAGS + ["-D" + d for d in args.defines]
-    run([sys.executable, os.path.join(HERE, "gen_fft.py"), os.path.join(HERE, "fft_codelets.h")])
+    if args.defines:
+        # a variant gets codelets of its own (the generator reads its options
+        # from the environment), so the default build's header stays as it is
+        header = os.path.join(build, "fft_codelets.h")
+        run([sys.executable, os.path.join(HERE, "gen_fft.py"), header])
+        flags.append(f'-DGSM_CODELETS="{header}"')
+    else:
+        run([sys.executable, os.path.join(HERE, "gen_fft.py"), os.path.join(HERE, "fft_codelets.h")])
 
     def compile_unit(u):
         obj = os.path.join(build, u.replace(".hip", ".o"))

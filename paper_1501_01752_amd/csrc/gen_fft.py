@@ -6,10 +6,12 @@ residues and a set of wanted output residues,
 
     out[j] = sum_{k in inputs} in[k] * exp(sign * 2 pi i * k * j / N),
 
-by mixed-radix decimation in time (radix 4, then 2, 3, 5), built as a
-data-flow graph of real additions and constant multiplications.  Zero inputs
-are propagated, multiplications by 0, +-1 and +-i disappear, and only the
-operations that feed a wanted output are emitted.  The result is a
+built as a data-flow graph of real additions and constant multiplications
+from several factorisations (decimation in time or in frequency, radix 4 or
+split radix, mixed radix 2, 3, 5 otherwise; each also by network
+transposition of the transposed problem), keeping the one with the fewest
+operations.  Zero inputs are propagated, multiplications by 0, +-1 and +-i
+disappear, and only the operations that feed a wanted output are emitted.  The result is a
 ``__device__ __forceinline__`` template over the real type (float or double)
 that works on register arrays, so every twiddle is a literal constant.
 
@@ -150,40 +152,145 @@ def _radix(n):
     raise ValueError(f'size {n} is not 2,3,5-smooth')
 
 
-def dft(b, xs, n, sign):
-    """Decimation in time; xs: list of n complex values (possibly zero)."""
+def _zeros(n):
+    return [C(ZERO, ZERO) for _ in range(n)]
+
+
+def _mul_i(b, x, s):
+    """x * (s i) for s = +1 or -1 (free: a swap and a sign)."""
+    if s > 0:
+        return C(neg(x.im), x.re)
+    return C(x.im, neg(x.re))
+
+
+def _butterfly(b, t, n, sign):
+    """Length-r DFT of the already twiddled t (r = len(t)) with the usual
+    shared partial sums for r = 2 and 4, plain sums otherwise."""
+    r = len(t)
+    if NAIVE_BUTTERFLIES:
+        r = -r
+    if r == 2:
+        return [cadd(b, t[0], t[1]), csub(b, t[0], t[1])]
+    if r == 4:
+        a0 = cadd(b, t[0], t[2])
+        a1 = csub(b, t[0], t[2])
+        a2 = cadd(b, t[1], t[3])
+        a3 = _mul_i(b, csub(b, t[1], t[3]), sign)
+        return [cadd(b, a0, a2), cadd(b, a1, a3), csub(b, a0, a2), csub(b, a1, a3)]
+    r = abs(r)
+    out = []
+    for q in range(r):
+        acc = C(ZERO, ZERO)
+        for j in range(r):
+            acc = cadd(b, acc, ctw(b, t[j], sign * j * q, r))
+        out.append(acc)
+    return out
+
+
+def dft_dit(b, xs, n, sign, split):
+    """Decimation in time (split radix 2/4 for powers of two when `split`,
+    else radix 4, 2, 3, 5); xs: n complex values (possibly zero)."""
     if n == 1:
         return list(xs)
     if all(x.is_zero() for x in xs):
-        return [C(ZERO, ZERO) for _ in range(n)]
-    r = _radix(n)
+        return _zeros(n)
+    if split and n % 4 == 0 and (n & (n - 1)) == 0:
+        e = dft_dit(b, xs[0::2], n // 2, sign, split)
+        o1 = dft_dit(b, xs[1::4], n // 4, sign, split)
+        o3 = dft_dit(b, xs[3::4], n // 4, sign, split)
+        out = [None] * n
+        q = n // 4
+        for k in range(q):
+            u = ctw(b, o1[k], sign * k, n)
+            v = ctw(b, o3[k], sign * 3 * k, n)
+            sm = cadd(b, u, v)
+            df = _mul_i(b, csub(b, u, v), sign)
+            out[k] = cadd(b, e[k], sm)
+            out[k + 2 * q] = csub(b, e[k], sm)
+            out[k + q] = cadd(b, e[k + q], df)
+            out[k + 3 * q] = csub(b, e[k + q], df)
+        return out
+    r = 2 if (split and n == 2) else _radix(n)
     m = n // r
-    subs = [dft(b, xs[j::r], m, sign) for j in range(r)]
+    subs = [dft_dit(b, xs[j::r], m, sign, split) for j in range(r)]
     out = [None] * n
     for k in range(m):
         t = [ctw(b, subs[j][k], sign * j * k, n) for j in range(r)]
-        for q in range(r):
-            acc = C(ZERO, ZERO)
-            for j in range(r):
-                acc = cadd(b, acc, ctw(b, t[j], sign * j * q, r))
-            out[k + q * m] = acc
+        for qq, v in enumerate(_butterfly(b, t, n, sign)):
+            out[k + qq * m] = v
     return out
+
+
+def dft_dif(b, xs, n, sign, split):
+    """Decimation in frequency, the transpose of dft_dit's factorisation."""
+    if n == 1:
+        return list(xs)
+    if all(x.is_zero() for x in xs):
+        return _zeros(n)
+    if split and n % 4 == 0 and (n & (n - 1)) == 0:
+        q = n // 4
+        ev = [cadd(b, xs[i], xs[i + 2 * q]) for i in range(2 * q)]
+        u1, u3 = [], []
+        for i in range(q):
+            a = csub(b, xs[i], xs[i + 2 * q])
+            c = _mul_i(b, csub(b, xs[i + q], xs[i + 3 * q]), sign)
+            u1.append(ctw(b, cadd(b, a, c), sign * i, n))
+            u3.append(ctw(b, csub(b, a, c), sign * 3 * i, n))
+        e = dft_dif(b, ev, 2 * q, sign, split)
+        o1 = dft_dif(b, u1, q, sign, split)
+        o3 = dft_dif(b, u3, q, sign, split)
+        out = [None] * n
+        for k in range(2 * q):
+            out[2 * k] = e[k]
+        for k in range(q):
+            out[4 * k + 1] = o1[k]
+            out[4 * k + 3] = o3[k]
+        return out
+    r = 2 if (split and n == 2) else _radix(n)
+    m = n // r
+    # butterflies across the r blocks of length m, twiddle, then r sub-DFTs
+    cols = []
+    for i in range(m):
+        t = [xs[i + j * m] for j in range(r)]
+        cols.append(_butterfly(b, t, n, sign))
+    out = [None] * n
+    for qq in range(r):
+        sub = [ctw(b, cols[i][qq], sign * qq * i, n) for i in range(m)]
+        y = dft_dif(b, sub, m, sign, split)
+        for k in range(m):
+            out[k * r + qq] = y[k]
+    return out
+
+
+def dft(b, xs, n, sign):
+    """Radix-4 decimation in time (the reference factorisation)."""
+    return dft_dit(b, xs, n, sign, False)
 
 
 # ------------------------------------------------------------- emitter ------
 
-def build_codelet(n, in_slots, out_slots, sign):
+ALGORITHMS = (('dit', False), ('dit', True), ('dif', False), ('dif', True))
+# Codelets longer than this are held whole in one lane (a full column of the
+# plane pass); there the fewest-operation forms need more registers than a
+# lane has and spill, while radix-4 decimation in time with plain butterfly
+# sums (more additions, shorter live ranges) fits: measured faster.
+LOW_PRESSURE_ABOVE = 32
+NAIVE_BUTTERFLIES = False
+
+
+def _build(n, in_slots, out_slots, sign, algo):
     b = Builder()
     xs = [C(ZERO, ZERO) for _ in range(n)]
     for i, s in enumerate(in_slots):
         xs[s] = C(b.inp(i, 0), b.inp(i, 1))
-    ys = dft(b, xs, n, sign)
+    kind, split = algo
+    ys = (dft_dit if kind == 'dit' else dft_dif)(b, xs, n, sign, split)
     outs = [ys[s] for s in out_slots]
     return b, outs
 
 
-def emit(name, n, in_slots, out_slots, sign):
-    b, outs = build_codelet(n, in_slots, out_slots, sign)
+def _live(b, outs):
+    """Nodes the outputs depend on."""
     nodes = b.g.nodes
     used = set()
     stack = []
@@ -201,6 +308,84 @@ def emit(name, n, in_slots, out_slots, sign):
             stack += [op[1], op[2]]
         elif op[0] == 'mul':
             stack.append(op[1])
+    return used
+
+
+def _ops(b, outs):
+    return sum(1 for i in _live(b, outs) if b.g.nodes[i][0] != 'in')
+
+
+def _transpose(b, outs, n_in):
+    """Network transposition.  The codelet is a real linear map from its
+    2 n_in input parts to the parts of `outs`; the transposed graph computes
+    the transposed map (for a DFT of sign s restricted to input set I and
+    output set O, that is the DFT of sign -s from O to I, the DFT matrix being
+    symmetric).  Every fan-out of the original becomes an addition."""
+    nodes = b.g.nodes
+    live = _live(b, outs)
+    t = Builder()
+    adj = {}
+
+    def contribute(i, ref):
+        if ref is ZERO:
+            return
+        adj[i] = ref if i not in adj else t.add(adj[i], ref)
+
+    for j, o in enumerate(outs):
+        for part, r in ((0, o.re), (1, o.im)):
+            if r is ZERO:
+                continue
+            x = t.inp(j, part)
+            contribute(r[0], neg(x) if r[1] else x)
+    res = [[ZERO, ZERO] for _ in range(n_in)]
+    for i in sorted(live, reverse=True):
+        if i not in adj:
+            continue
+        a = adj[i]
+        op = nodes[i]
+        if op[0] == 'add':
+            contribute(op[1], a)
+            contribute(op[2], a)
+        elif op[0] == 'sub':
+            contribute(op[1], a)
+            contribute(op[2], neg(a))
+        elif op[0] == 'mul':
+            contribute(op[1], t.mul(a, float(op[2])))
+        else:  # input
+            res[op[1]][op[2]] = a
+    return t, [C(r[0], r[1]) for r in res]
+
+
+def build_codelet(n, in_slots, out_slots, sign, min_ops=False):
+    """The cheapest (fewest real operations after pruning) of: the
+    decimation-in-time and -in-frequency factorisations, radix 4 or split
+    radix, built directly for this pattern of non-zero inputs and wanted
+    outputs, and the transposes of the same factorisations built for the
+    transposed pattern (output set to input set, opposite sign).  Above
+    LOW_PRESSURE_ABOVE only the plain radix-4 form is built."""
+    global NAIVE_BUTTERFLIES
+    best = None
+    saved = NAIVE_BUTTERFLIES
+    algos = ALGORITHMS
+    if n > LOW_PRESSURE_ABOVE and not min_ops:
+        NAIVE_BUTTERFLIES = True
+        algos = (('dit', False),)
+    for algo in algos:
+        cands = [_build(n, in_slots, out_slots, sign, algo)]
+        tb, touts = _build(n, out_slots, in_slots, -sign, algo)
+        cands.append(_transpose(tb, touts, len(out_slots)))
+        for b, outs in cands:
+            cost = _ops(b, outs)
+            if best is None or cost < best[0]:
+                best = (cost, b, outs)
+    NAIVE_BUTTERFLIES = saved
+    return best[1], best[2]
+
+
+def emit(name, n, in_slots, out_slots, sign):
+    b, outs = build_codelet(n, in_slots, out_slots, sign)
+    nodes = b.g.nodes
+    used = _live(b, outs)
     lines = []
     nin, nout = len(in_slots), len(out_slots)
     lines.append(f'// {name}: N={n}, {nin} non-zero inputs, {nout} outputs, sign {sign:+d}')
@@ -320,8 +505,9 @@ def main(path):
 
 def opcount_table():
     """Real operations (add, sub, mul each one) of the unsplit pruned length-P
-    transforms for orders |k| <= K: the algorithmic work of one expand and one
-    crop, for every supported P and every K <= (P - 1) / 4."""
+    transforms for orders |k| <= K in their fewest-operation factorisation:
+    the algorithmic work of one expand and one crop, for every supported P
+    and every K <= (P - 1) / 4."""
     lines = ['// Generated by gen_fft.py: real operations of pruned length-P DFTs. Do not edit.',
              '#pragma once', '',
              '// kPrunedOps[log2(P) - 2][K] = {expand (2K+1 -> P), crop (P -> 2K+1)}',
@@ -332,9 +518,11 @@ def opcount_table():
         for k in range(32):
             if k <= (p - 1) // 4:
                 i, o = expand_slots(p, k)
-                fe = emit('e', p, i, o, +1)[1]
+                b, outs = build_codelet(p, i, o, +1, min_ops=True)
+                fe = _ops(b, outs)
                 i, o = crop_slots(p, k)
-                fc = emit('c', p, i, o, -1)[1]
+                b, outs = build_codelet(p, i, o, -1, min_ops=True)
+                fc = _ops(b, outs)
             else:
                 fe = fc = 0
             vals.append(f'{{{fe}, {fc}}}')
