@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--config-steps", type=int, default=5, help="steps of the 4-solve case")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed codelet families instead of timing them at the first solve")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="REPS",
                     help="for hardware-counter runs: a 1 GiB device copy (calibration), then REPS "
                          "batched operator applications of one body of the step in complex64 and "
@@ -65,13 +67,13 @@ def parse():
     return ap.parse_args()
 
 
-def build_workload(gsm, inputs, directions):
+def build_workload(gsm, inputs, directions, autotune=False):
     bodies = [inputs.sphere_lattice_m15(), inputs.layered_stack_m15()]
     work = []
     for w in bodies:
         lam, M = w["wavelength"], w["M"]
         k0 = 2 * np.pi / lam
-        plan = gsm.Plan(w["eps"], w["period"], M)
+        plan = gsm.Plan(w["eps"], w["period"], M, autotune=autotune)
         insts = []
         dirs = [np.array([0.0, 0.0, 1.0])]
         if directions:
@@ -231,7 +233,7 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no HIP device"}))
         sys.exit(1)
-    work = build_workload(gsm, inputs, args.directions)
+    work = build_workload(gsm, inputs, args.directions, autotune=not args.no_autotune)
     if args.matvec_only:
         matvec_only(gsm, work[0], args.matvec_only)
         return
@@ -317,6 +319,8 @@ def main():
                                f"2 transverse drives x (normal incidence + {args.directions} seeded directions) "
                                "per body, batched; complex64 GMRES(30) + FP64 refinement to 1e-9",
                    "solves_per_step": per_step, "max_rel_residual": worst,
+                   "codelet_families": {name: work[i][0].tuning(work[i][1][0].M)[0]
+                                        for i, name in enumerate(("sphere", "stack"))},
                    "per_solve_mean": krylov},
         "roofline": roofline,
         "fp64_gpu_solve": fp64,

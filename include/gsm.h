@@ -87,11 +87,21 @@ typedef struct gsm_geometry {
   const double* eps; /* host, Vz*Vy*Vx real values > 0, x fastest; copied */
 } gsm_geometry;
 
+/* gsm_plan_opts.flags */
+enum {
+  GSM_PLAN_AUTOTUNE = 1 /* time the codelet families of each FFT stage at the
+                           first use of an (M, P, precision) and keep the
+                           fastest (else fixed defaults) */
+};
+
 typedef struct gsm_plan_opts {
-  int32_t m_max[3]; /* largest order count M_a any instance will use (0..31) */
-  int32_t device;   /* HIP device ordinal */
-  int32_t flags;    /* reserved, must be 0 */
-  int32_t reserved;
+  int32_t m_max[3];       /* largest order count M_a any instance will use (0..31) */
+  int32_t device;         /* HIP device ordinal */
+  int32_t flags;          /* GSM_PLAN_AUTOTUNE or 0 */
+  int32_t reserved;       /* must be 0 */
+  const char* tune_cache; /* NULL, or a text file of tuning results: read at
+                             plan creation (entries of this device's
+                             architecture), extended with each new tuning */
 } gsm_plan_opts;
 
 /* One (omega, k) point.  Harmonics m_a run over [-M_a, M_a] (the paper's
@@ -233,6 +243,13 @@ int gsm_eff_tensor_vjp(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst
                        const gsm_solver_opts* opts, const double* E_save,
                        const double* eps_eff, const double* gbar, double* grad_vox, void* ws,
                        size_t ws_bytes, gsm_solve_info* info, void* stream);
+
+/* Codelet families (0: fewest operations, 1: plain radix 4) used for the
+ * orders M with the precision given, per FFT stage: fam[0] pass A (z),
+ * fam[1] pass B rows (x), fam[2] pass B columns (y), fam[3] pass C (z).
+ * *tuned = 1 when they come from timing (this plan or its cache file),
+ * 0 for the fixed defaults. */
+int gsm_plan_tuning(gsm_plan_t plan, const int32_t M[3], int32_t precision, int32_t fam[4], int32_t* tuned);
 
 /* ------------------------------------------------------------ profiling */
 

@@ -58,7 +58,21 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Grid {
   double* g64 = nullptr;
   float* g32 = nullptr;
+  // codelet families per FFT stage (pass A, pass B rows, pass B columns,
+  // pass C) for complex64 [0] and complex128 [1]; tuned[k] once timed
+  int fam[2][4] = {};
+  bool tuned[2] = {false, false};
 };
+
+// Fixed families when not tuned (measured at M = 15, P = 64): the whole
+// columns of the complex64 plane pass use the plain radix-4 codelets (the
+// fewest-operation ones spill there), and so does complex128 pass C.
+void default_families(int P, bool dbl, int* fam) {
+  fam[0] = 0;
+  fam[1] = 0;
+  fam[2] = (!dbl && P == 64) ? 1 : 0;
+  fam[3] = dbl ? 1 : 0;
+}
 
 }  // namespace
 
@@ -86,6 +100,11 @@ struct gsm_plan_s {
   double2* d_coef = nullptr;
   std::map<std::array<int, 4>, Grid> grids;
   RunSlot slots[kSlots];
+  bool autotune = false;
+  std::string tune_cache;  // file of tuning results ("" = none)
+  std::string arch;        // device architecture name, the cache's key
+  // cached tuning results by (M, P, precision)
+  std::map<std::array<int, 5>, std::array<int, 4>> tune_known;
 };
 
 namespace {
@@ -114,7 +133,8 @@ int check_plan_opts(const gsm_plan_opts* o) {
   for (int a = 0; a < 3; ++a)
     if (o->m_max[a] < 0 || o->m_max[a] > kMaxOrder)
       return fail(GSM_E_UNSUPPORTED, "m_max[%d]=%d outside [0, %d]", a, o->m_max[a], kMaxOrder);
-  if (o->flags != 0) return fail(GSM_E_ARG, "plan flags must be 0");
+  if (o->flags & ~GSM_PLAN_AUTOTUNE) return fail(GSM_E_ARG, "unknown plan flags");
+  if (o->reserved != 0) return fail(GSM_E_ARG, "reserved plan field must be 0");
   return GSM_OK;
 }
 
@@ -451,6 +471,14 @@ int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** 
   HIP_TRY(hipFree(blk));
   HIP_TRY(hipFree(t1));
   HIP_TRY(hipFree(t2));
+  for (int d = 0; d < 2; ++d) {
+    default_families(P, d == 1, g.fam[d]);
+    auto tk = plan->tune_known.find({M[0], M[1], M[2], P, d});
+    if (tk != plan->tune_known.end()) {
+      for (int k = 0; k < 4; ++k) g.fam[d][k] = tk->second[k];
+      g.tuned[d] = true;
+    }
+  }
   plan->grids[key] = g;
   *out = &plan->grids[key];
   return GSM_OK;
@@ -509,6 +537,7 @@ PassArgs<T> pass_args(const Group& g, const Grid* grid) {
   a.st = g.st;
   a.t = (cplx<T>*)g.T;
   a.grid = sizeof(T) == 8 ? (const T*)grid->g64 : (const T*)grid->g32;
+  for (int k = 0; k < 4; ++k) a.fam[k] = grid->fam[sizeof(T) == 8 ? 1 : 0][k];
   a.partial = g.partc;
   return a;
 }
@@ -679,6 +708,114 @@ int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step
                     [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_c<T>(with_ev(a, e0, e1), st); },
                     nf * pf.c, pf.c));
   return GSM_OK;
+}
+
+// ----------------------------------------------------------- autotuner --
+// At the first use of an (M, P, precision) by a plan made with
+// GSM_PLAN_AUTOTUNE: time every codelet family of each FFT stage on the
+// group's own batch (zeroed buffers: the kernels' speed does not depend on
+// the data), the best of five launches each, and keep the fastest, leaving
+// the default unless another family is at least 3 % faster (single launches
+// of a few tens of microseconds vary by about that much); record the result
+// in the plan's cache file if it has one.
+template <typename T>
+int tune_families(gsm_plan_s* plan, Group& g, Grid* grid, int restart, hipStream_t st) {
+  const int d = sizeof(T) == 8 ? 1 : 0;
+  if (!plan->autotune || grid->tuned[d]) return GSM_OK;
+  const long long n = g.shape.n;
+  const int S = g.shape.S;
+  HIP_TRY(hipMemsetAsync(g.V, 0, (size_t)S * (restart + 1) * n * sizeof(cplx<T>), st));
+  HIP_TRY(hipMemsetAsync(g.T, 0, (size_t)S * g.shape.tsize * sizeof(cplx<T>), st));
+  PassArgs<T> a = pass_args<T>(g, grid);
+  a.g.nblk_c = nblk_c_for(g.shape, d == 1);
+  a.x = (cplx<T>*)g.V;
+  a.xs = (long long)(restart + 1) * n;
+  a.y = a.x + n;
+  a.ys = a.xs;
+  a.gate = GATE_NONE;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto best_of = [&](auto launch, float* ms) -> int {
+    *ms = 1e30f;
+    for (int r = 0; r < 5; ++r) {
+      HIP_TRY(hipEventRecord(e0, st));
+      HIP_TRY(launch());
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float t = 0;
+      HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+      *ms = std::min(*ms, t);
+    }
+    return GSM_OK;
+  };
+  int fam[4];
+  float tA[2], tB[4], tC[2];
+  int rc = GSM_OK;
+  for (int f = 0; f < 2 && !rc; ++f) {
+    PassArgs<T> q = a;
+    q.mode = 0;
+    q.fam[0] = f;
+    rc = best_of([&] { return launch_pass_a<T>(q, st); }, &tA[f]);
+  }
+  for (int f = 0; f < 4 && !rc; ++f) {
+    PassArgs<T> q = a;
+    q.fam[1] = f / 2;
+    q.fam[2] = f % 2;
+    rc = best_of([&] { return launch_pass_b<T>(q, st); }, &tB[f]);
+  }
+  for (int f = 0; f < 2 && !rc; ++f) {
+    PassArgs<T> q = a;
+    q.mode = PC_GREEN;
+    q.fam[3] = f;
+    rc = best_of([&] { return launch_pass_c<T>(q, st); }, &tC[f]);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  int def[4];
+  default_families(g.shape.P, d == 1, def);
+  auto pick = [](const float* t, int n, int dflt) {
+    int best = dflt;
+    for (int f = 0; f < n; ++f)
+      if (t[f] < 0.97f * t[dflt] && t[f] < t[best]) best = f;
+    return best;
+  };
+  fam[0] = pick(tA, 2, def[0]);
+  const int fb = pick(tB, 4, def[1] * 2 + def[2]);
+  fam[1] = fb / 2;
+  fam[2] = fb % 2;
+  fam[3] = pick(tC, 2, def[3]);
+  for (int k = 0; k < 4; ++k) grid->fam[d][k] = fam[k];
+  grid->tuned[d] = true;
+  const int* M = g.shape.M;
+  plan->tune_known[{M[0], M[1], M[2], g.shape.P, d}] = {fam[0], fam[1], fam[2], fam[3]};
+  if (!plan->tune_cache.empty()) {
+    if (FILE* f = std::fopen(plan->tune_cache.c_str(), "a")) {
+      std::fprintf(f, "%s P=%d M=%d,%d,%d %s S=%d fam=%d,%d,%d,%d us=%.1f,%.1f,%.1f\n", plan->arch.c_str(),
+                   g.shape.P, M[0], M[1], M[2], d ? "c128" : "c64", S, fam[0], fam[1], fam[2], fam[3],
+                   1e3 * tA[fam[0]], 1e3 * tB[fb], 1e3 * tC[fam[3]]);
+      std::fclose(f);
+    }
+  }
+  return GSM_OK;
+}
+
+// Entries of a tuning cache file for this architecture.
+void read_tune_cache(gsm_plan_s* plan) {
+  FILE* f = std::fopen(plan->tune_cache.c_str(), "r");
+  if (!f) return;
+  char line[512], arch[128], prec[8];
+  while (std::fgets(line, sizeof line, f)) {
+    int P, M0, M1, M2, S, a, b, c, e;
+    if (std::sscanf(line, "%127s P=%d M=%d,%d,%d %7s S=%d fam=%d,%d,%d,%d", arch, &P, &M0, &M1, &M2, prec, &S, &a,
+                    &b, &c, &e) != 11)
+      continue;
+    if (plan->arch != arch) continue;
+    const int d = std::strcmp(prec, "c128") == 0 ? 1 : 0;
+    plan->tune_known[{M0, M1, M2, P, d}] = {a & 1, b & 1, c & 1, e & 1};
+  }
+  std::fclose(f);
 }
 
 #ifndef GSM_LEAD
@@ -1039,6 +1176,9 @@ int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& g
   for (size_t i = 0; i < groups.size(); ++i) {
     Grid* grid = nullptr;
     if ((rc = ensure_grid(plan, groups[i].shape.M, groups[i].shape.P, st, &grid))) return rc;
+    rc = fp64 ? tune_families<double>(plan, groups[i], grid, so->restart, st)
+              : tune_families<float>(plan, groups[i], grid, so->restart, st);
+    if (rc) return rc;
     grids[i] = grid;
   }
   rc = fp64 ? run_groups<double>(plan, sys, groups, grids, so, E_out, out_host, exp, st, rhs)
@@ -1157,6 +1297,20 @@ int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out
   if (opts->device < 0 || opts->device >= ndev) return fail(GSM_E_ARG, "device %d not present", opts->device);
   auto* p = new gsm_plan_s();
   p->device = opts->device;
+  p->autotune = (opts->flags & GSM_PLAN_AUTOTUNE) != 0;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, opts->device) == hipSuccess) {
+      p->arch = prop.gcnArchName;
+      const size_t colon = p->arch.find(':');
+      if (colon != std::string::npos) p->arch.resize(colon);
+    }
+    if (p->arch.empty()) p->arch = "unknown";
+  }
+  if (opts->tune_cache) {
+    p->tune_cache = opts->tune_cache;
+    read_tune_cache(p);
+  }
   for (int a = 0; a < 3; ++a) {
     p->period[a] = geo->period[a];
     p->vox[a] = geo->nvox[a];
@@ -1235,6 +1389,31 @@ int gsm_plan_destroy(gsm_plan_t p) {
     if (sl.stream) hipStreamDestroy(sl.stream);
   }
   delete p;
+  return GSM_OK;
+}
+
+int gsm_plan_tuning(gsm_plan_t p, const int32_t M[3], int32_t precision, int32_t fam[4], int32_t* tuned) {
+  if (!p || !M || !fam) return fail(GSM_E_ARG, "NULL argument");
+  if (precision != GSM_MIXED && precision != GSM_FP64) return fail(GSM_E_ARG, "unknown precision %d", precision);
+  const int P = fft_size_for(M);
+  if (P < 0) return fail(GSM_E_UNSUPPORTED, "no FFT size for these orders");
+  const int d = precision == GSM_FP64 ? 1 : 0;
+  int f[4];
+  int t = 0;
+  auto g = p->grids.find({M[0], M[1], M[2], P});
+  if (g != p->grids.end()) {
+    for (int k = 0; k < 4; ++k) f[k] = g->second.fam[d][k];
+    t = g->second.tuned[d];
+  } else {
+    default_families(P, d == 1, f);
+    auto tk = p->tune_known.find({M[0], M[1], M[2], P, d});
+    if (tk != p->tune_known.end()) {
+      for (int k = 0; k < 4; ++k) f[k] = tk->second[k];
+      t = 1;
+    }
+  }
+  for (int k = 0; k < 4; ++k) fam[k] = f[k];
+  if (tuned) *tuned = t;
   return GSM_OK;
 }
 

@@ -270,11 +270,12 @@ def dft(b, xs, n, sign):
 # ------------------------------------------------------------- emitter ------
 
 ALGORITHMS = (('dit', False), ('dit', True), ('dif', False), ('dif', True))
-# Codelets longer than this are held whole in one lane (a full column of the
-# plane pass); there the fewest-operation forms need more registers than a
-# lane has and spill, while radix-4 decimation in time with plain butterfly
-# sums (more additions, shorter live ranges) fits: measured faster.
-LOW_PRESSURE_ABOVE = 32
+# Two families of every codelet: 0 = the fewest operations over the
+# factorisations below; 1 = radix-4 decimation in time with plain butterfly
+# sums (more additions, shorter live ranges, so fewer registers where a whole
+# long transform sits in one lane).  The kernels take the family as a
+# template parameter and the library's autotuner picks per pass by timing.
+FAMILIES = (0, 1)
 NAIVE_BUTTERFLIES = False
 
 
@@ -356,24 +357,25 @@ def _transpose(b, outs, n_in):
     return t, [C(r[0], r[1]) for r in res]
 
 
-def build_codelet(n, in_slots, out_slots, sign, min_ops=False):
+def build_codelet(n, in_slots, out_slots, sign, family=0):
     """The cheapest (fewest real operations after pruning) of: the
     decimation-in-time and -in-frequency factorisations, radix 4 or split
     radix, built directly for this pattern of non-zero inputs and wanted
     outputs, and the transposes of the same factorisations built for the
-    transposed pattern (output set to input set, opposite sign).  Above
-    LOW_PRESSURE_ABOVE only the plain radix-4 form is built."""
+    transposed pattern (output set to input set, opposite sign).  Family 1
+    is the plain radix-4 form only."""
     global NAIVE_BUTTERFLIES
     best = None
     saved = NAIVE_BUTTERFLIES
     algos = ALGORITHMS
-    if n > LOW_PRESSURE_ABOVE and not min_ops:
+    if family == 1:
         NAIVE_BUTTERFLIES = True
         algos = (('dit', False),)
     for algo in algos:
         cands = [_build(n, in_slots, out_slots, sign, algo)]
-        tb, touts = _build(n, out_slots, in_slots, -sign, algo)
-        cands.append(_transpose(tb, touts, len(out_slots)))
+        if family == 0:
+            tb, touts = _build(n, out_slots, in_slots, -sign, algo)
+            cands.append(_transpose(tb, touts, len(out_slots)))
         for b, outs in cands:
             cost = _ops(b, outs)
             if best is None or cost < best[0]:
@@ -382,8 +384,8 @@ def build_codelet(n, in_slots, out_slots, sign, min_ops=False):
     return best[1], best[2]
 
 
-def emit(name, n, in_slots, out_slots, sign):
-    b, outs = build_codelet(n, in_slots, out_slots, sign)
+def emit(name, n, in_slots, out_slots, sign, family=0):
+    b, outs = build_codelet(n, in_slots, out_slots, sign, family)
     nodes = b.g.nodes
     used = _live(b, outs)
     lines = []
@@ -466,8 +468,8 @@ def twiddle_table(n):
     return f'__device__ constexpr double kTw{n}[{n}][2] = {{\n{body}\n}};\n'
 
 
-def dispatch(name, n, nin, nout, kind, param):
-    return (f'template <> struct Codelet{kind}<{n}, {param}> {{\n'
+def dispatch(name, n, nin, nout, kind, param, family):
+    return (f'template <> struct Codelet{kind}<{n}, {param}, {family}> {{\n'
             f'  template <typename T> __device__ static __forceinline__ void run('
             f'const T (&ir)[{nin}], const T (&ii)[{nin}], T (&orr)[{nout}], T (&oi)[{nout}]) {{\n'
             f'    {name}<T>(ir, ii, orr, oi);\n  }}\n}};\n')
@@ -481,20 +483,23 @@ def main(path):
            '// CodeletC<N, K>: all N inputs, outputs at residues of -K..K,',
            '//   out[k] = sum_j in[j] exp(-2 pi i k j / N).',
            '// CodeletF<N, S>: full transform with sign S (+1 or -1).',
-           'template <int N, int K> struct CodeletE;',
-           'template <int N, int K> struct CodeletC;',
-           'template <int N, int S> struct CodeletF;', '']
+           '// The last parameter is the family: 0 fewest operations, 1 plain radix 4.',
+           'template <int N, int K, int F> struct CodeletE;',
+           'template <int N, int K, int F> struct CodeletC;',
+           'template <int N, int S, int F> struct CodeletF;', '']
     total = 0
-    for name, n, i, o, s in codelet_specs():
-        src, nf = emit(name, n, i, o, s)
-        out.append(src)
-        total += nf
-        if name.startswith('fft_e'):
-            out.append(dispatch(name, n, len(i), len(o), 'E', (len(i) - 1) // 2))
-        elif name.startswith('fft_c'):
-            out.append(dispatch(name, n, len(i), len(o), 'C', (len(o) - 1) // 2))
-        else:
-            out.append(dispatch(name, n, len(i), len(o), 'F', s))
+    for family in FAMILIES:
+        for name, n, i, o, s in codelet_specs():
+            fname = f'{name}_f{family}'
+            src, nf = emit(fname, n, i, o, s, family)
+            out.append(src)
+            total += nf
+            if name.startswith('fft_e'):
+                out.append(dispatch(fname, n, len(i), len(o), 'E', (len(i) - 1) // 2, family))
+            elif name.startswith('fft_c'):
+                out.append(dispatch(fname, n, len(i), len(o), 'C', (len(o) - 1) // 2, family))
+            else:
+                out.append(dispatch(fname, n, len(i), len(o), 'F', s, family))
     for n in (8, 16, 32, 64, 128):
         out.append(twiddle_table(n))
     with open(path, 'w') as f:
@@ -518,10 +523,10 @@ def opcount_table():
         for k in range(32):
             if k <= (p - 1) // 4:
                 i, o = expand_slots(p, k)
-                b, outs = build_codelet(p, i, o, +1, min_ops=True)
+                b, outs = build_codelet(p, i, o, +1, 0)
                 fe = _ops(b, outs)
                 i, o = crop_slots(p, k)
-                b, outs = build_codelet(p, i, o, -1, min_ops=True)
+                b, outs = build_codelet(p, i, o, -1, 0)
                 fc = _ops(b, outs)
             else:
                 fe = fc = 0

@@ -110,6 +110,7 @@ struct PassArgs {
   int mode;
   int gate;
   hipEvent_t ev0, ev1;  // when set: stamped at the start and end of the launch
+  int fam[4];           // codelet family per stage: pass A, pass B rows, pass B columns, pass C
 };
 
 // ---- launchers (passes.hip) ----

@@ -20,6 +20,7 @@ GSM_MIXED, GSM_FP64 = 0, 1
 GSM_GMRES, GSM_BICGSTAB = 0, 1
 GSM_OUT_HOST = 1
 GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT = 0, 1
+GSM_PLAN_AUTOTUNE = 1
 
 
 class Geometry(C.Structure):
@@ -28,7 +29,7 @@ class Geometry(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("m_max", C.c_int32 * 3), ("device", C.c_int32), ("flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 class Instance(C.Structure):
@@ -76,6 +77,8 @@ _SIGS = {
     "gsm_plan": (C.c_int, [C.POINTER(Geometry), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
     "gsm_plan_destroy": (C.c_int, [C.c_void_p]),
     "gsm_plan_coefficients": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsm_plan_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]),
     "gsm_plan_contrast_grid": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_void_p]),
     "gsm_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance),
                                      C.POINTER(SolverOpts), C.POINTER(C.c_size_t)]),
@@ -195,7 +198,8 @@ def _stream(stream):
 class Plan:
     """Owning handle of a gsm_plan_t built from a voxel body."""
 
-    def __init__(self, eps, period=(1.0, 1.0, 1.0), m_max=(15, 15, 15), device=0):
+    def __init__(self, eps, period=(1.0, 1.0, 1.0), m_max=(15, 15, 15), device=0, autotune=False,
+                 tune_cache=None):
         self.eps = np.ascontiguousarray(eps, dtype=np.float64)
         vz, vy, vx = self.eps.shape
         g = Geometry()
@@ -207,6 +211,9 @@ class Plan:
         for a in range(3):
             o.m_max[a] = int(m_max[a])
         o.device = device
+        o.flags = GSM_PLAN_AUTOTUNE if autotune else 0
+        self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+        o.tune_cache = self._tune_cache
         h = C.c_void_p()
         _check(lib().gsm_plan(C.byref(g), C.byref(o), C.byref(h)), allow_warn=False)
         self.handle = h
@@ -225,6 +232,14 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def tuning(self, M, precision=GSM_MIXED):
+        """(families per FFT stage [pass A, pass B rows, pass B columns,
+        pass C], tuned?) for the orders M in that precision."""
+        fam = (C.c_int32 * 4)()
+        tuned = C.c_int32()
+        _check(lib().gsm_plan_tuning(self.handle, (C.c_int32 * 3)(*M), precision, fam, C.byref(tuned)))
+        return list(fam), bool(tuned.value)
 
     def coefficients(self):
         n = [4 * m + 1 for m in self.m_max]
