@@ -53,6 +53,8 @@ def parse():
                     help="seeded incidence directions per body besides normal incidence (batched)")
     ap.add_argument("--config-steps", type=int, default=5, help="steps of the 4-solve case")
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--sweep-steps", type=int, default=2,
+                    help="steps of the uneven 256-instance sweep (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed codelet families instead of timing them at the first solve")
@@ -107,6 +109,37 @@ def run_step(gsm, work, opts):
                 STATS[k] += i[k]
         STATS["solves"] += len(info)
     return nsolve, worst
+
+
+def uneven_sweep(gsm, inputs, steps, autotune):
+    """256 (omega, k) points of an orthorhombic ellipsoid lattice (1 : 0.8 :
+    1.2, semi-axes 0.35 / 0.25 / 0.15, eps 6, 64^3 voxels) with order counts
+    drawn from 6..16 per point, one drive each: one call, its eleven (M, P)
+    groups scheduled by the library; complex64 + FP64 refinement to 1e-9."""
+    import torch
+    lam, khat, Ms = inputs.orthorhombic_sweep()
+    period = (1.0, 0.8, 1.2)
+    eps = inputs.ellipsoid((64, 64, 64), period, (0.35, 0.25, 0.15), 6.0)
+    plan = gsm.Plan(eps, period, (16, 16, 16), autotune=autotune)
+    insts = []
+    for i in range(lam.size):
+        k = 2 * np.pi / lam[i] * khat[i]
+        inst = gsm.make_instance(lam[i], k, (int(Ms[i]),) * 3, [tuple(inputs.transverse_drive(khat[i]))])
+        inst.eps_b = plan.basis_eps(inst)
+        insts.append(inst)
+    opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30)
+    plan.solve(insts, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info, st = plan.solve(insts, opts)
+        if st != gsm.GSM_OK:
+            raise RuntimeError(f"sweep status {st}")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"value": round(len(insts) / dt, 3), "unit": "solves/s", "instances": len(insts),
+            "order_counts": [int(Ms.min()), int(Ms.max())], "ms_per_step": round(dt * 1e3, 3),
+            "max_rel_residual": max(i["rel_residual"] for i in info)}
 
 
 def cpu_baseline(inputs):
@@ -306,6 +339,7 @@ def main():
                          "solves_per_step": ns // args.config_steps,
                          "ms_per_step": round((t4 - t3) / args.config_steps * 1e3, 3)}
 
+    sweep = uneven_sweep(gsm, inputs, args.sweep_steps, not args.no_autotune) if args.sweep_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     per_step = total // args.steps
     line = {
@@ -325,6 +359,7 @@ def main():
         "roofline": roofline,
         "fp64_gpu_solve": fp64,
         "as_configured": as_configured,
+        "uneven_sweep": sweep,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
