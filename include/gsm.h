@@ -201,7 +201,9 @@ int gsm_workspace_size(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst
  * batched into the same kernel launches.  E_out receives the fields
  * (complex128, layout above); info (host, one per system) the per-system
  * results.  Returns the worst status.  Synchronises `stream` before
- * returning. */
+ * returning.  n_inst must be >= 1 (GSM_E_ARG otherwise, nothing launched);
+ * with opts->x0 the refinement starts from that field, and one that already
+ * meets the tolerance is returned unchanged after one FP64 residual check. */
 int gsm_solve(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
               const gsm_solver_opts* opts, void* ws, size_t ws_bytes, double* E_out,
               gsm_solve_info* info, void* stream);

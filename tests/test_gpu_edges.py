@@ -1,0 +1,134 @@
+"""Edge cases of the HIP solve against the CPU oracle: empty batch, warm
+starts, host output, a single harmonic, a zero order count on one axis,
+GMRES(1), identical systems in one batch, and a basis permittivity on the
+light cone."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from gpu_common import asym_body, k_vector, oracle_case, rel_err, say
+from oracle import gsm as O
+from paper_1501_01752_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def G():
+    from paper_1501_01752_amd import gsm
+    return gsm
+
+
+def _small():
+    gsm = G()
+    w = inputs.sphere_lattice_small()
+    k = k_vector(w["wavelength"], w["k_hat"])
+    plan = gsm.Plan(w["eps"], w["period"], w["M"])
+    inst = gsm.make_instance(w["wavelength"], k, w["M"], [(1, 0, 0), (0, 0.3, 1j)])
+    inst.eps_b = plan.basis_eps(inst)
+    c, q = oracle_case(w["eps"], w["period"], w["wavelength"], k, w["M"])
+    ref = O.solve_dense(c, w["M"], q, inst.eps_b, [np.array([1, 0, 0]), np.array([0, 0.3, 1j])]).ravel()
+    return gsm, plan, inst, ref
+
+
+def test_empty_batch_is_an_argument_error():
+    gsm, plan, inst, ref = _small()
+    say("solve of an empty batch")
+    with pytest.raises(gsm.GsmError) as e:
+        plan.solve([], gsm.default_opts())
+    assert e.value.status == gsm.GSM_E_ARG
+
+
+def test_warm_start_at_the_solution_returns_it():
+    gsm, plan, inst, ref = _small()
+    say("solve, then warm start at the result")
+    E, info, st = plan.solve([inst], gsm.default_opts(tol=1e-12))
+    assert st == gsm.GSM_OK
+    E2, info2, st2 = plan.solve([inst], gsm.default_opts(tol=1e-10), x0=E)
+    assert st2 == gsm.GSM_OK
+    assert all(i["iterations"] == 0 and i["refinements"] == 1 for i in info2)
+    assert np.array_equal(E2.cpu().numpy(), E.cpu().numpy())
+
+
+def test_warm_start_near_the_solution_converges():
+    import torch
+    gsm, plan, inst, ref = _small()
+    rng = np.random.default_rng(3)
+    x0 = ref + 1e-3 * np.abs(ref).max() * (rng.normal(size=ref.size) + 1j * rng.normal(size=ref.size))
+    say("warm start near the solution")
+    E, info, st = plan.solve([inst], gsm.default_opts(tol=1e-12), x0=torch.from_numpy(x0).cuda())
+    assert st == gsm.GSM_OK
+    assert rel_err(E.cpu().numpy(), ref) <= 1e-10
+
+
+def test_host_output_equals_device_output():
+    gsm, plan, inst, ref = _small()
+    opts = gsm.default_opts(tol=1e-12)
+    say("solve to device memory")
+    E, _, _ = plan.solve([inst], opts)
+    opts_h = gsm.default_opts(tol=1e-12)
+    opts_h.flags = gsm.GSM_OUT_HOST
+    arr = gsm.instances_array([inst])
+    out = np.zeros(ref.size, dtype=np.complex128)
+    info = (gsm.SolveInfo * 2)()
+    ws = plan.workspace([inst], opts_h)
+    say("solve to host memory")
+    st = gsm.lib().gsm_solve(plan.handle, 1, arr, C.byref(opts_h), C.c_void_p(ws.data_ptr()), ws.numel(),
+                             out.ctypes.data_as(C.c_void_p), info, None)
+    assert st == gsm.GSM_OK
+    assert np.array_equal(out, E.cpu().numpy())
+
+
+@pytest.mark.parametrize("M", [(0, 0, 0), (2, 0, 1)])
+def test_degenerate_order_counts_vs_dense(M):
+    gsm = G()
+    eps = asym_body()
+    period, lam = (1.0, 0.9, 1.1), 1 / 0.35
+    k = k_vector(lam, (0.3, 0.4, 0.866))
+    plan = gsm.Plan(eps, period, (2, 2, 2))
+    inst = gsm.make_instance(lam, k, M, [(0.2, 1.0, -0.4j), (1, 0, 0)])
+    inst.eps_b = plan.basis_eps(inst)
+    say(f"solve with M={M}")
+    E, info, st = plan.solve([inst], gsm.default_opts(tol=1e-12))
+    assert st == gsm.GSM_OK
+    c, q = oracle_case(eps, period, lam, k, M)
+    ref = O.solve_dense(c, M, q, inst.eps_b, [np.array([0.2, 1.0, -0.4j]), np.array([1, 0, 0])])
+    assert rel_err(E.cpu().numpy(), ref.ravel()) <= 1e-10
+
+
+def test_gmres_restart_one():
+    gsm, plan, inst, ref = _small()
+    say("GMRES(1)")
+    E, info, st = plan.solve([inst], gsm.default_opts(tol=1e-11, restart=1, max_iter=20000, max_refine=20000))
+    assert st == gsm.GSM_OK
+    assert rel_err(E.cpu().numpy(), ref) <= 1e-9
+
+
+def test_identical_systems_give_identical_fields():
+    gsm, plan, inst, ref = _small()
+    say("three identical instances in one batch")
+    E, info, st = plan.solve([inst, inst, inst], gsm.default_opts(tol=1e-12))
+    assert st == gsm.GSM_OK
+    E = E.cpu().numpy().reshape(3, -1)
+    assert np.array_equal(E[0], E[1]) and np.array_equal(E[0], E[2])
+    assert rel_err(E[0], ref) <= 1e-10
+
+
+def test_basis_permittivity_on_the_light_cone_is_refused():
+    gsm = G()
+    lam = 1 / 0.3
+    plan = gsm.Plan(np.full((8, 8, 8), 2.0), (1, 1, 1), (1, 1, 1))
+    # |q_0|^2 = 1 at normal incidence from vacuum: eps_b = 1 makes G(q_0) singular
+    inst = gsm.make_instance(lam, k_vector(lam, (0, 0, 1)), (1, 1, 1), [(1, 0, 0)])
+    inst.eps_b = 1.0
+    say("explicit eps_b on the light cone")
+    with pytest.raises(gsm.GsmError) as e:
+        plan.solve([inst], gsm.default_opts())
+    assert e.value.status == gsm.GSM_E_SINGULAR
