@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--sweep-steps", type=int, default=2,
                     help="steps of the uneven 256-instance sweep (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="residual reduction asked of each complex64 Krylov cycle (library default if unset)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed codelet families instead of timing them at the first solve")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="REPS",
@@ -270,7 +272,8 @@ def main():
     if args.matvec_only:
         matvec_only(gsm, work[0], args.matvec_only)
         return
-    opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30)
+    extra = {} if args.inner_tol is None else {"inner_tol": args.inner_tol}
+    opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30, **extra)
     for _ in range(args.warmup):
         run_step(gsm, work, opts)
     torch.cuda.synchronize()
