@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each complex64 Krylov cycle (library default if unset)")
+    ap.add_argument("--serial-bodies", action="store_true",
+                    help="solve the two bodies of a step one after the other (default: concurrently, "
+                         "one host thread and stream each)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed codelet families instead of timing them at the first solve")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="REPS",
@@ -97,11 +100,37 @@ def build_workload(gsm, inputs, directions, autotune=False):
 STATS = {"iterations": 0, "refinements": 0, "reorth": 0, "solves": 0}
 
 
-def run_step(gsm, work, opts):
+class Bodies:
+    """Runs the bodies of a step (one plan each) from one host thread per
+    body, each on a stream of its own, so their launches interleave on the
+    GPU; serial=True solves them one after the other instead."""
+
+    def __init__(self, work, serial=False):
+        import torch
+        from concurrent.futures import ThreadPoolExecutor
+        self.work = work
+        self.serial = serial
+        self.streams = [torch.cuda.Stream() for _ in work]
+        self.pool = None if serial else ThreadPoolExecutor(len(work))
+
+    def _one(self, i, opts):
+        import torch
+        plan, insts = self.work[i]
+        s = self.streams[i]
+        with torch.cuda.stream(s):
+            return plan.solve(insts, opts, stream=s.cuda_stream)
+
+    def solve(self, opts):
+        if self.serial:
+            return [self._one(i, opts) for i in range(len(self.work))]
+        futs = [self.pool.submit(self._one, i, opts) for i in range(len(self.work))]
+        return [f.result() for f in futs]
+
+
+def run_step(gsm, bodies, opts):
     nsolve = 0
     worst = 0.0
-    for plan, insts in work:
-        E, info, st = plan.solve(insts, opts)
+    for E, info, st in bodies.solve(opts):
         if st != gsm.GSM_OK:
             raise RuntimeError(f"solve status {st}: {info}")
         nsolve += len(info)
@@ -269,19 +298,20 @@ def main():
         print(json.dumps({"error": "no HIP device"}))
         sys.exit(1)
     work = build_workload(gsm, inputs, args.directions, autotune=not args.no_autotune)
+    bodies = Bodies(work, serial=args.serial_bodies)
     if args.matvec_only:
         matvec_only(gsm, work[0], args.matvec_only)
         return
     extra = {} if args.inner_tol is None else {"inner_tol": args.inner_tol}
     opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30, **extra)
     for _ in range(args.warmup):
-        run_step(gsm, work, opts)
+        run_step(gsm, bodies, opts)
     torch.cuda.synchronize()
 
     # one extra step with every kernel class timed: the per-class table and
     # the dominant class
     gsm.profile_begin()
-    run_step(gsm, work, opts)
+    run_step(gsm, bodies, opts)
     kernels = kernel_table(gsm.profile_end())
     dom_name = next(iter(kernels))
     dom_class = dom_name.rsplit("_", 1)[0]
@@ -294,7 +324,7 @@ def main():
     total = 0
     worst = 0.0
     for _ in range(args.steps):
-        n, w = run_step(gsm, work, opts)
+        n, w = run_step(gsm, bodies, opts)
         total += n
         worst = max(worst, w)
     torch.cuda.synchronize()
@@ -315,12 +345,12 @@ def main():
     fp64 = None
     if args.fp64_steps > 0:
         opts64 = gsm.default_opts(tol=TOL, precision=gsm.GSM_FP64, restart=30)
-        run_step(gsm, work, opts64)
+        run_step(gsm, bodies, opts64)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         n64 = 0
         for _ in range(args.fp64_steps):
-            n, _ = run_step(gsm, work, opts64)
+            n, _ = run_step(gsm, bodies, opts64)
             n64 += n
         torch.cuda.synchronize()
         fp64 = {"value": round(n64 / (time.perf_counter() - t2), 3), "unit": "solves/s"}
@@ -328,7 +358,7 @@ def main():
     # the literal 4-solve case: x, y drives at normal incidence, both bodies
     as_configured = None
     if args.config_steps > 0:
-        small = build_workload(gsm, inputs, 0)
+        small = Bodies(build_workload(gsm, inputs, 0, autotune=not args.no_autotune), serial=args.serial_bodies)
         run_step(gsm, small, opts)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
@@ -358,6 +388,7 @@ def main():
                    "solves_per_step": per_step, "max_rel_residual": worst,
                    "codelet_families": {name: work[i][0].tuning(work[i][1][0].M)[0]
                                         for i, name in enumerate(("sphere", "stack"))},
+                   "bodies": "serial" if args.serial_bodies else "concurrent (one host thread and stream each)",
                    "per_solve_mean": krylov},
         "roofline": roofline,
         "fp64_gpu_solve": fp64,

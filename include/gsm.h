@@ -39,7 +39,8 @@
  * - No call throws or aborts; every failure is a negative status and
  *   gsm_last_error() (thread-local) holds a message.  On error the outputs
  *   are left untouched, except GSM_W_* results, which are written.
- * - A plan is used by one host thread / stream at a time.
+ * - A plan is used by one host thread / stream at a time; different plans
+ *   may be used from different host threads at once.
  */
 #ifndef GSM_H
 #define GSM_H
@@ -268,7 +269,8 @@ typedef struct gsm_kernel_stat {
   double flops;     /* algorithmic real floating-point operations (FFT passes) */
 } gsm_kernel_stat;
 
-/* Start collecting (clears earlier records).  Not thread-safe. */
+/* Start collecting (clears earlier records).  Calls on different plans may
+ * run on several host threads meanwhile; start and end are made from one. */
 int gsm_profile_begin(void);
 /* The same, recording only the launches of one kernel class, given by its
  * name without the precision suffix (e.g. "pass_b"), so that a timed run

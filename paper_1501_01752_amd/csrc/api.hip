@@ -12,7 +12,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -584,16 +586,21 @@ struct ProfRec {
   double funit;   // operations per working system (step records)
 };
 
+// Shared by every host thread that calls the library (calls on different
+// plans may run concurrently): records are guarded by a mutex; the tag of the
+// group whose work a thread is issuing is the thread's own.
 struct Profiler {
-  bool on = false;
+  std::atomic<bool> on{false};
   int only = -1;  // record only this base class (-1: all)
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  int group_tag = 0;    // tag of the group whose work is being issued
-  int tag_counter = 0;  // source of group tags
+  std::atomic<int> tag_counter{0};  // source of group tags
+  std::mutex mu;
 } g_prof;
+thread_local int t_group_tag = 0;  // tag of the group whose work this thread issues
 
+// a pair of pooled events (callers hold g_prof.mu)
 hipEvent_t prof_event() {
   if (g_prof.used == g_prof.pool.size()) {
     hipEvent_t e;
@@ -607,12 +614,19 @@ template <class F>
 hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f,
                  double flops = 0.0, double funit = 0.0) {
   if (!g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f();
-  ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag,
-            flops, funit};
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit};
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    r.a = prof_event();
+    r.b = prof_event();
+  }
   if (r.a) hipEventRecord(r.a, st);
   const hipError_t e = f();
   if (r.b) hipEventRecord(r.b, st);
-  if (r.a && r.b) g_prof.recs.push_back(r);
+  if (r.a && r.b) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.recs.push_back(r);
+  }
   return e;
 }
 
@@ -622,10 +636,15 @@ template <class F>
 hipError_t timed_ext(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f, double flops,
                      double funit) {
   if (!g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f(nullptr, nullptr);
-  ProfRec r{cls * 2 + (dbl ? 1 : 0), prof_event(), prof_event(), bytes, step, unit, g_prof.group_tag,
-            flops, funit};
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit};
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    r.a = prof_event();
+    r.b = prof_event();
+  }
   if (!r.a || !r.b) return f(nullptr, nullptr);
   const hipError_t e = f(r.a, r.b);
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.recs.push_back(r);
   return e;
 }
@@ -634,8 +653,9 @@ hipError_t timed_ext(int cls, bool dbl, double bytes, int step, double unit, hip
 // steps were done by system s.
 void prof_resolve(const int* jdone, int S, long long n, size_t vb) {
   if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   for (auto& r : g_prof.recs) {
-    if (r.group != g_prof.group_tag || r.step == -1) continue;
+    if (r.group != t_group_tag || r.step == -1) continue;
     double tot = 0;
     if (r.step == -2) {
       for (int s = 0; s < S; ++s)
@@ -1002,7 +1022,7 @@ struct GroupRun {
   // Issue everything that needs no wait; *moved says whether anything was.
   int advance(bool* moved) {
     *moved = false;
-    g_prof.group_tag = tag;
+    t_group_tag = tag;
     int rc = GSM_OK;
     switch (phase) {
       case START:
@@ -1626,10 +1646,11 @@ int gsm_profile_begin_only(const char* cls) {
       if (std::strcmp(cls, kClassNames[c]) == 0) only = c;
     if (only < 0) return fail(GSM_E_ARG, "unknown kernel class '%s'", cls);
   }
-  g_prof.on = true;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.only = only;
   g_prof.recs.clear();
   g_prof.used = 0;
+  g_prof.on = true;
   return GSM_OK;
 }
 
@@ -1637,6 +1658,7 @@ int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out) {
   if (!g_prof.on) return fail(GSM_E_ARG, "profiling was not started");
   g_prof.on = false;
   HIP_TRY(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   std::vector<gsm_kernel_stat> st(2 * K_NBASE);
   for (int c = 0; c < 2 * K_NBASE; ++c) {
     std::memset(&st[c], 0, sizeof st[c]);
