@@ -74,7 +74,20 @@ enum { GSM_MIXED = 0, GSM_FP64 = 1 };
  * which then only sizes the workspace) */
 enum { GSM_GMRES = 0, GSM_BICGSTAB = 1 };
 /* gsm_solver_opts.flags */
-enum { GSM_OUT_HOST = 1 /* E_out / eps_eff / grad are host pointers */ };
+enum {
+  GSM_OUT_HOST = 1,   /* E_out / eps_eff / grad are host pointers */
+  GSM_SOLVE_GRAPH = 2 /* issue GMRES steps as captured launch graphs (see below) */
+};
+/* Launch graphs.  With GSM_SOLVE_GRAPH (and launch profiling off) the
+ * Arnoldi steps of a GMRES cycle are issued as captured HIP graphs of four
+ * steps each (one graph launch instead of about nine kernel launches per
+ * step).  A plan keeps the instantiated graphs of its recent groups and
+ * reuses one when a later call would issue exactly the same launches (same
+ * kernel arguments: same plan, workspace address, group composition and
+ * options), so repeated solves of one batch pay the capture once.  Results
+ * are identical to those of separate launches.  BiCGStab steps are always
+ * separate launches.  Off by default: on the MI355X with ROCm 7.2 the graph
+ * launches ran 3-9 % slower than separate launches for these kernels. */
 /* gsm_apply modes */
 enum { GSM_APPLY_FORWARD = 0, GSM_APPLY_ADJOINT = 1 };
 
@@ -247,6 +260,11 @@ int gsm_eff_tensor_vjp(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst
                        const double* eps_eff, const double* gbar, double* grad_vox, void* ws,
                        size_t ws_bytes, gsm_solve_info* info, void* stream);
 
+/* Launch graphs of a plan so far: *captured = graphs captured and
+ * instantiated, *launched = graph launches (each runs a few Krylov steps of
+ * one group).  Either pointer may be NULL.  GSM_E_ARG for a NULL plan. */
+int gsm_plan_graph_stats(gsm_plan_t plan, int64_t* captured, int64_t* launched);
+
 /* Codelet families (0: fewest operations, 1: plain radix 4) used for the
  * orders M with the precision given, per FFT stage: fam[0] pass A (z),
  * fam[1] pass B rows (x), fam[2] pass B columns (y), fam[3] pass C (z).
@@ -277,6 +295,11 @@ int gsm_profile_begin(void);
  * carries one event pair per launch of that class only.  GSM_E_ARG for an
  * unknown name. */
 int gsm_profile_begin_only(const char* kernel_class);
+/* The same (kernel_class may be NULL: every class), timing only one launch
+ * in `every` of each class, counted in launch order from this call (the
+ * first launch of a class is timed); the statistics cover the timed launches
+ * only.  GSM_E_ARG for every < 1 or an unknown name. */
+int gsm_profile_begin_sampled(const char* kernel_class, int32_t every);
 /* Stop, synchronise the device, write up to `max` entries to out and the
  * number of classes seen to *n_out. */
 int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out);

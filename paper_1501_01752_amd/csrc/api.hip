@@ -90,7 +90,16 @@ struct RunSlot {
   int* h_inner = nullptr;         // pinned [cap]: cycle still running (written by kernels)
   void* h_exp = nullptr;          // pinned [cap] per-system results
   int cap = 0;
+  // instantiated launch graphs of Krylov steps, keyed by the bytes of every
+  // kernel argument they were captured with (least recently used evicted)
+  struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long used = 0;
+  };
+  std::vector<GraphEntry> graphs;
 };
+constexpr size_t kGraphsPerSlot = 32;
 
 struct gsm_plan_s {
   int device = 0;
@@ -107,6 +116,9 @@ struct gsm_plan_s {
   std::string arch;        // device architecture name, the cache's key
   // cached tuning results by (M, P, precision)
   std::map<std::array<int, 5>, std::array<int, 4>> tune_known;
+  long long graph_captures = 0, graph_launches = 0;
+  unsigned long long graph_clock = 0;  // use counter for the graph caches
+  bool graph_off = false;              // set if a capture ever fails: separate launches from then on
 };
 
 namespace {
@@ -174,7 +186,7 @@ int check_solver_opts(const gsm_solver_opts* s) {
   if (s->method != GSM_GMRES && s->method != GSM_BICGSTAB) return fail(GSM_E_ARG, "unknown method %d", s->method);
   if (s->method == GSM_BICGSTAB && s->restart < 5)
     return fail(GSM_E_ARG, "BiCGStab keeps six vectors per system: restart must be >= 5");
-  if (s->flags & ~GSM_OUT_HOST) return fail(GSM_E_ARG, "unknown solver flags");
+  if (s->flags & ~(GSM_OUT_HOST | GSM_SOLVE_GRAPH)) return fail(GSM_E_ARG, "unknown solver flags");
   return GSM_OK;
 }
 
@@ -592,6 +604,8 @@ struct ProfRec {
 struct Profiler {
   std::atomic<bool> on{false};
   int only = -1;  // record only this base class (-1: all)
+  int every = 1;  // time one launch in `every` of each class
+  std::atomic<unsigned> seq[K_NBASE] = {};  // launches of each class seen
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -599,6 +613,7 @@ struct Profiler {
   std::mutex mu;
 } g_prof;
 thread_local int t_group_tag = 0;  // tag of the group whose work this thread issues
+thread_local bool t_capturing = false;  // this thread is capturing a launch graph: no timing events
 
 // a pair of pooled events (callers hold g_prof.mu)
 hipEvent_t prof_event() {
@@ -613,7 +628,8 @@ hipEvent_t prof_event() {
 template <class F>
 hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f,
                  double flops = 0.0, double funit = 0.0) {
-  if (!g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f();
+  if (t_capturing || !g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f();
+  if (g_prof.every > 1 && g_prof.seq[cls].fetch_add(1) % g_prof.every != 0) return f();
   ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit};
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -635,7 +651,8 @@ hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStre
 template <class F>
 hipError_t timed_ext(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f, double flops,
                      double funit) {
-  if (!g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f(nullptr, nullptr);
+  if (t_capturing || !g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f(nullptr, nullptr);
+  if (g_prof.every > 1 && g_prof.seq[cls].fetch_add(1) % g_prof.every != 0) return f(nullptr, nullptr);
   ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit};
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -842,6 +859,11 @@ void read_tune_cache(gsm_plan_s* plan) {
 #define GSM_LEAD 2
 #endif
 constexpr int kLead = GSM_LEAD;  // Arnoldi steps the host may run ahead of the device
+#ifndef GSM_CHUNK
+#define GSM_CHUNK 4
+#endif
+constexpr int kChunk = GSM_CHUNK;  // Arnoldi steps per launch graph
+constexpr int kChunkLead = 2;      // graphs the host may run ahead of the device
 
 __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, SysExport* out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -863,9 +885,13 @@ __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, S
 
 // The solve of one group as a state machine the scheduler advances without
 // blocking: FP64 residual check -> Krylov cycle (Arnoldi steps or BiCGStab
-// iterations issued at most kLead ahead of the device; the host stops when
-// the kernels' pinned per-system flags say every cycle has ended) -> residual
-// check ... -> export of the results.  Everything runs on the slot's stream.
+// iterations issued at most kLead ahead of the device, or GMRES steps as
+// launch graphs of kChunk steps at most kChunkLead graphs ahead; the host
+// stops when the kernels' pinned per-system flags say every cycle has ended)
+// -> residual check ... -> export of the results.  Everything runs on the
+// slot's stream.  Steps issued after a system's cycle ended return at once
+// for that system (the kernels test its flags), so a graph may run past the
+// end of a cycle.
 template <typename T>
 struct GroupRun {
   enum Phase { START, RESID_WAIT, CYCLE, EXPORT_WAIT, DONE };
@@ -897,6 +923,8 @@ struct GroupRun {
 
   Phase phase = START;
   int outer = 0, j = 0, n_outer = 0;
+  bool graph = false;              // GMRES steps issued as cached launch graphs
+  std::vector<unsigned char> fp;   // bytes of the step launches' fixed arguments
 
   void setup(const Grid* grid) {
     S = g->shape.S;
@@ -939,6 +967,20 @@ struct GroupRun {
       par_host.push_back((*sys)[si].par);
       off_host.push_back((*sys)[si].out_off);
     }
+    // Launch graphs need every kernel argument of a step to follow from
+    // these bytes and the step index; timed launches carry events and are
+    // not captured.
+    graph = !bicg && (so->flags & GSM_SOLVE_GRAPH) && !g_prof.on && !plan->graph_off;
+    if (graph) {
+      auto add = [&](const void* q, size_t b) {
+        fp.insert(fp.end(), (const unsigned char*)q, (const unsigned char*)q + b);
+      };
+      const int ints[4] = {r_pa, m, (int)sizeof(T), adjoint ? 1 : 0};
+      add(ints, sizeof ints);
+      add(&kt, sizeof kt);
+      add(&p, sizeof p);
+      add(&st, sizeof st);
+    }
   }
 
   int issue_residual() {
@@ -975,7 +1017,9 @@ struct GroupRun {
     return GSM_OK;
   }
 
-  int issue_step() {
+  // The launches of one Arnoldi (or BiCGStab) step; the step counter
+  // advances, no event is recorded.
+  int step_kernels() {
     if (bicg) {
       const int it = j;
       pbi.x = V + BI_P * n;
@@ -1006,8 +1050,67 @@ struct GroupRun {
       HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, st); }));
       HIP_TRY(timed(K_CGS_RE, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_second_pass<T>(kt, j, st); }));
     }
-    HIP_TRY(hipEventRecord(sl->step_ev[j % kRing], st));
     ++j;
+    return GSM_OK;
+  }
+
+  int issue_step() {
+    const int rc = step_kernels();
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(sl->step_ev[(j - 1) % kRing], st));
+    return GSM_OK;
+  }
+
+  // Steps j .. j + cnt - 1 as one launch graph: the slot's cached graph of
+  // exactly these launches if there is one, else captured from the stream
+  // now.  Records the chunk's event (chunk index j / kChunk).
+  int issue_chunk(int cnt) {
+    const int c = j / kChunk;
+    std::vector<unsigned char> key = fp;
+    const int tail[2] = {j, cnt};
+    key.insert(key.end(), (const unsigned char*)tail, (const unsigned char*)tail + sizeof tail);
+    RunSlot::GraphEntry* hit = nullptr;
+    for (auto& e : sl->graphs)
+      if (e.key == key) hit = &e;
+    if (hit) {
+      j += cnt;
+    } else {
+      const int j0 = j;
+      HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      t_capturing = true;
+      int rc = GSM_OK;
+      for (int q = 0; q < cnt && !rc; ++q) rc = step_kernels();
+      t_capturing = false;
+      hipGraph_t gr = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &gr);
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ei = (rc || ec != hipSuccess) ? hipErrorUnknown : hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      if (gr) (void)hipGraphDestroy(gr);
+      if (rc || ec != hipSuccess || ei != hipSuccess) {
+        // not capturable here: separate launches for the rest of the plan's life
+        (void)hipGetLastError();
+        plan->graph_off = true;
+        graph = false;
+        j = j0;
+        for (int q = 0; q < cnt; ++q)
+          if ((rc = step_kernels())) return rc;
+        HIP_TRY(hipEventRecord(sl->step_ev[c % kRing], st));
+        return GSM_OK;
+      }
+      if (sl->graphs.size() >= kGraphsPerSlot) {
+        auto old = std::min_element(sl->graphs.begin(), sl->graphs.end(),
+                                    [](const RunSlot::GraphEntry& a, const RunSlot::GraphEntry& b) { return a.used < b.used; });
+        (void)hipGraphExecDestroy(old->exec);
+        sl->graphs.erase(old);
+      }
+      sl->graphs.push_back(RunSlot::GraphEntry{std::move(key), ex, 0});
+      hit = &sl->graphs.back();
+      ++plan->graph_captures;
+    }
+    hit->used = ++plan->graph_clock;
+    HIP_TRY(hipGraphLaunch(hit->exec, st));
+    ++plan->graph_launches;
+    HIP_TRY(hipEventRecord(sl->step_ev[c % kRing], st));
     return GSM_OK;
   }
 
@@ -1064,6 +1167,24 @@ struct GroupRun {
             *moved = true;
             return end_cycle();
           }
+          if (graph) {
+            // chunks of kChunk steps; the host runs kChunkLead chunks ahead
+            const int c = j / kChunk;
+            if (c >= kChunkLead) {
+              const hipError_t q = hipEventQuery(sl->step_ev[(c - kChunkLead) % kRing]);
+              if (q == hipErrorNotReady) return GSM_OK;
+              HIP_TRY(q);
+              bool running = false;
+              for (int s = 0; s < S && !running; ++s) running = sl->h_inner[s] != 0;
+              if (!running) {
+                *moved = true;
+                return end_cycle();
+              }
+            }
+            if ((rc = issue_chunk(std::min(kChunk, limit - j)))) return rc;
+            *moved = true;
+            continue;
+          }
           if (j >= kLead) {
             const hipError_t q = hipEventQuery(sl->step_ev[(j - kLead) % kRing]);
             if (q == hipErrorNotReady) return GSM_OK;
@@ -1096,6 +1217,7 @@ struct GroupRun {
 
   // the event a blocked run waits on
   hipEvent_t blocker() const {
+    if (phase == CYCLE && graph) return sl->step_ev[(j / kChunk - kChunkLead + kRing) % kRing];
     if (phase == CYCLE) return sl->step_ev[(j - kLead + kRing) % kRing];
     return sl->phase_ev;
   }
@@ -1403,12 +1525,20 @@ int gsm_plan_destroy(gsm_plan_t p) {
     if (sl.h_flags) hipHostFree(sl.h_flags);
     if (sl.h_inner) hipHostFree(sl.h_inner);
     if (sl.h_exp) hipHostFree(sl.h_exp);
+    for (auto& ge : sl.graphs) hipGraphExecDestroy(ge.exec);
     for (auto& e : sl.step_ev)
       if (e) hipEventDestroy(e);
     if (sl.phase_ev) hipEventDestroy(sl.phase_ev);
     if (sl.stream) hipStreamDestroy(sl.stream);
   }
   delete p;
+  return GSM_OK;
+}
+
+int gsm_plan_graph_stats(gsm_plan_t p, int64_t* captured, int64_t* launched) {
+  if (!p) return fail(GSM_E_ARG, "NULL plan");
+  if (captured) *captured = p->graph_captures;
+  if (launched) *launched = p->graph_launches;
   return GSM_OK;
 }
 
@@ -1637,9 +1767,12 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
   return worst;
 }
 
-int gsm_profile_begin(void) { return gsm_profile_begin_only(nullptr); }
+int gsm_profile_begin(void) { return gsm_profile_begin_sampled(nullptr, 1); }
 
-int gsm_profile_begin_only(const char* cls) {
+int gsm_profile_begin_only(const char* cls) { return gsm_profile_begin_sampled(cls, 1); }
+
+int gsm_profile_begin_sampled(const char* cls, int32_t every) {
+  if (every < 1) return fail(GSM_E_ARG, "sampling period %d must be >= 1", every);
   int only = -1;
   if (cls) {
     for (int c = 0; c < K_NBASE; ++c)
@@ -1648,6 +1781,8 @@ int gsm_profile_begin_only(const char* cls) {
   }
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.only = only;
+  g_prof.every = every;
+  for (auto& q : g_prof.seq) q = 0;
   g_prof.recs.clear();
   g_prof.used = 0;
   g_prof.on = true;

@@ -18,7 +18,7 @@ GSM_E_ARG, GSM_E_NONFINITE, GSM_E_NOMEM, GSM_E_DEVICE = -1, -2, -3, -4
 GSM_E_SINGULAR, GSM_E_WORKSPACE, GSM_E_UNSUPPORTED = -5, -6, -7
 GSM_MIXED, GSM_FP64 = 0, 1
 GSM_GMRES, GSM_BICGSTAB = 0, 1
-GSM_OUT_HOST = 1
+GSM_OUT_HOST, GSM_SOLVE_GRAPH = 1, 2
 GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT = 0, 1
 GSM_PLAN_AUTOTUNE = 1
 
@@ -77,6 +77,7 @@ _SIGS = {
     "gsm_plan": (C.c_int, [C.POINTER(Geometry), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
     "gsm_plan_destroy": (C.c_int, [C.c_void_p]),
     "gsm_plan_coefficients": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsm_plan_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gsm_plan_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]),
     "gsm_plan_contrast_grid": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_void_p]),
@@ -98,6 +99,7 @@ _SIGS = {
                                      C.c_void_p]),
     "gsm_profile_begin": (C.c_int, []),
     "gsm_profile_begin_only": (C.c_int, [C.c_char_p]),
+    "gsm_profile_begin_sampled": (C.c_int, [C.c_char_p, C.c_int32]),
     "gsm_profile_end": (C.c_int, [C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]),
 }
 
@@ -124,10 +126,13 @@ def _check(status, allow_warn=True):
     return status
 
 
-def profile_begin(only=None):
+def profile_begin(only=None, every=1):
     """Start per-launch timing of every kernel class, or of the class `only`
-    (a name such as "pass_b", both precisions)."""
-    if only is None:
+    (a name such as "pass_b", both precisions); every > 1 times one launch in
+    `every` of each class."""
+    if every != 1:
+        _check(lib().gsm_profile_begin_sampled(None if only is None else only.encode(), every))
+    elif only is None:
         _check(lib().gsm_profile_begin())
     else:
         _check(lib().gsm_profile_begin_only(only.encode()))
@@ -240,6 +245,12 @@ class Plan:
         tuned = C.c_int32()
         _check(lib().gsm_plan_tuning(self.handle, (C.c_int32 * 3)(*M), precision, fam, C.byref(tuned)))
         return list(fam), bool(tuned.value)
+
+    def graph_stats(self):
+        """(launch graphs captured, graph launches) of this plan so far."""
+        cap, run = C.c_int64(), C.c_int64()
+        _check(lib().gsm_plan_graph_stats(self.handle, C.byref(cap), C.byref(run)))
+        return cap.value, run.value
 
     def coefficients(self):
         n = [4 * m + 1 for m in self.m_max]

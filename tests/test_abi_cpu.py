@@ -122,3 +122,11 @@ def test_validate_auto_eps_b_dodges_light_cone():
     lam = 1 / 0.3
     inst = gsm.make_instance(lam, (0, 0, 2 * np.pi / lam), (3, 3, 3))
     assert _validate(g, _popts(), [inst]) == gsm.GSM_OK
+
+
+def test_profile_sampling_arguments():
+    L = gsm.lib()
+    assert L.gsm_profile_begin_sampled(b"pass_b", 0) == gsm.GSM_E_ARG
+    assert L.gsm_profile_begin_sampled(None, -3) == gsm.GSM_E_ARG
+    assert L.gsm_profile_begin_sampled(b"no_such_class", 2) == gsm.GSM_E_ARG
+    assert L.gsm_plan_graph_stats(None, None, None) == gsm.GSM_E_ARG
