@@ -34,7 +34,7 @@ def test_every_class_counted():
     finally:
         stats = gsm.profile_end()
     assert st == gsm.GSM_OK
-    for c in ("pass_a_c64", "pass_b_c64", "pass_c_c64", "cgs_dot_c64", "cgs_update_c64", "pass_a_c128"):
+    for c in ("pass_a_c64", "pass_b_c64", "pass_c_c64", "cgs_update_c64", "cgs_finish_c64", "pass_a_c128"):
         assert c in stats and stats[c]["launches"] > 0 and stats[c]["ms"] > 0, c
     # the three passes run together: one launch each per operator application
     assert stats["pass_a_c64"]["launches"] == stats["pass_b_c64"]["launches"] == stats["pass_c_c64"]["launches"]
