@@ -144,3 +144,36 @@ def test_no_graph_for_bicgstab_timed_launches_or_by_default():
     say("gmres without the flag: separate launches")
     _, _, st = plan.solve(insts, gsm.default_opts(tol=1e-11))
     assert st == gsm.GSM_OK and plan.graph_stats() == (0, 0)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_graph_adjoint_solve_equals_separate_launches(precision):
+    """The adjoint Arnoldi steps (Green tensor before the convolution) in
+    launch graphs: the same bits as separate launches, on the capture and on
+    a replay, and the dense adjoint solution of the oracle."""
+    import torch
+    from gpu_common import seeded_field, to_torch
+    gsm = G()
+    eps = asym_body()
+    period, lam, M = (1.0, 0.9, 1.1), 1 / 0.35, (2, 1, 3)
+    k = k_vector(lam, (0.3, 0.4, 0.866))
+    inst = gsm.make_instance(lam, k, M, [(1, 0, 0), (0, 1, 0)])
+    plan = gsm.Plan(eps, period, M)
+    inst.eps_b = plan.basis_eps(inst)
+    rhs = seeded_field((2, 3, 2 * M[2] + 1, 2 * M[1] + 1, 2 * M[0] + 1), seed=29)
+    prec = gsm.GSM_FP64 if precision == "fp64" else gsm.GSM_MIXED
+    kw = dict(tol=1e-12, precision=prec)
+    say(f"adjoint, separate launches, {precision}")
+    ref_gpu, _, st = plan.solve_adjoint([inst], to_torch(rhs.ravel()), gsm.default_opts(**kw))
+    assert st == gsm.GSM_OK
+    for call in ("capture", "replay"):
+        say(f"adjoint, launch graphs ({call}), {precision}")
+        got, _, st = plan.solve_adjoint([inst], to_torch(rhs.ravel()),
+                                        gsm.default_opts(flags=gsm.GSM_SOLVE_GRAPH, **kw))
+        assert st == gsm.GSM_OK and torch.equal(got, ref_gpu), call
+    cap, run = plan.graph_stats()
+    assert cap > 0 and run > cap
+    c, q = oracle_case(eps, period, lam, k, M)
+    A = O.assemble_dense(c, M, q, inst.eps_b)
+    ref = np.linalg.solve(A.conj().T, rhs.reshape(2, -1).T).T
+    assert rel_err(ref_gpu.cpu().numpy(), ref.ravel()) <= 1e-10
