@@ -192,22 +192,40 @@ int check_solver_opts(const gsm_solver_opts* s) {
 
 // -------------------------------------------------- basis permittivity ----
 
-// min over the truncated harmonic set of | |q_m|^2 - eb | (one linear scan)
+// min over the truncated harmonic set of | |q_m|^2 - eb |.  For fixed
+// (my, mz), g(mx) = (q0x + mx bx)^2 + r is a convex quadratic in mx, so over
+// the integers of [-Mx, Mx] |g| is smallest next to a root of g, next to its
+// vertex (g > 0 everywhere), or at an end of the range (the roots outside
+// it): at most eight candidates per (my, mz) instead of the whole row, each
+// evaluated as in a full scan, so the minimum is the same number.
 double margin_scan(const gsm_instance& in, const double* period, double eb) {
   const double k0 = 2.0 * M_PI / in.wavelength;
   double q0[3], b[3];
   for (int a = 0; a < 3; ++a) {
     q0[a] = in.k_inc[a] / k0;
-    b[a] = in.wavelength / period[a];
+    b[a] = in.wavelength / period[a];  // > 0
   }
+  const int Mx = in.M[0];
+  auto clampi = [&](double v) { return v < -Mx ? -Mx : (v > Mx ? Mx : (int)v); };
+  const double fv = std::floor(-q0[0] / b[0]);  // the vertex lies in [fv, fv + 1]
   double m = INFINITY;
   for (int mz = -in.M[2]; mz <= in.M[2]; ++mz) {
     const double qz = q0[2] + mz * b[2];
     for (int my = -in.M[1]; my <= in.M[1]; ++my) {
       const double qy = q0[1] + my * b[1];
       const double r = qy * qy + qz * qz - eb;
-      for (int mx = -in.M[0]; mx <= in.M[0]; ++mx) {
-        const double qx = q0[0] + mx * b[0];
+      int c[8] = {-Mx, Mx, clampi(fv), clampi(fv + 1), 0, 0, 0, 0};
+      int nc = 4;
+      if (r < 0) {
+        const double sr = std::sqrt(-r);
+        const double f1 = std::floor((sr - q0[0]) / b[0]), f2 = std::floor((-sr - q0[0]) / b[0]);
+        c[nc++] = clampi(f1);
+        c[nc++] = clampi(f1 + 1);
+        c[nc++] = clampi(f2);
+        c[nc++] = clampi(f2 + 1);
+      }
+      for (int i = 0; i < nc; ++i) {
+        const double qx = q0[0] + c[i] * b[0];
         m = std::min(m, std::fabs(qx * qx + r));
       }
     }

@@ -130,3 +130,41 @@ def test_profile_sampling_arguments():
     assert L.gsm_profile_begin_sampled(None, -3) == gsm.GSM_E_ARG
     assert L.gsm_profile_begin_sampled(b"no_such_class", 2) == gsm.GSM_E_ARG
     assert L.gsm_plan_graph_stats(None, None, None) == gsm.GSM_E_ARG
+
+
+def _brute_margin(lam, k_inc, M, period, eb):
+    """min over the truncated harmonic set of | |q_m|^2 - eb |, every harmonic."""
+    k0 = 2 * np.pi / lam
+    ax = [np.asarray(k_inc[a]) / k0 + np.arange(-M[a], M[a] + 1) * lam / period[a] for a in range(3)]
+    q2 = ax[0][None, None, :] ** 2 + ax[1][None, :, None] ** 2 + ax[2][:, None, None] ** 2
+    return float(np.abs(q2 - eb).min())
+
+
+def test_light_cone_check_matches_every_harmonic():
+    """The light-cone refusal for an explicit eps_b (|q_m|^2 within 1e-3 eps_b
+    of eps_b for some harmonic) against a scan of every harmonic: random
+    lattices, directions, order counts and eps_b, plus eps_b placed on a
+    shell and just inside and outside the 1e-3 band around it."""
+    rng = np.random.default_rng(17)
+    checked = 0
+    for t in range(300):
+        period = tuple(0.3 + 1.5 * rng.random(3))
+        M = tuple(int(v) for v in rng.integers(0, 7, 3))
+        lam = 0.5 + 4 * rng.random()
+        d = rng.normal(size=3)
+        if t % 4 == 0:
+            d[:2] = 0.0  # normal incidence
+        k_inc = (1.0 if t % 3 else 2.5 * rng.random()) * 2 * np.pi / lam * d / np.linalg.norm(d)
+        g, keep = _geom(np.full((2, 2, 2), 2.0), period)
+        po = _popts(tuple(max(m, 1) for m in M))
+        k0 = 2 * np.pi / lam
+        m = [int(rng.integers(-M[a], M[a] + 1)) for a in range(3)]
+        shell = sum((k_inc[a] / k0 + m[a] * lam / period[a]) ** 2 for a in range(3))
+        for eb in (0.3 + 8 * rng.random(), shell, shell * (1 + 0.5e-3), shell * (1 - 2e-3), shell * (1 + 2e-3)):
+            if eb <= 0:
+                continue
+            inst = gsm.make_instance(lam, k_inc, M, eps_b=eb)
+            want = gsm.GSM_E_SINGULAR if _brute_margin(lam, k_inc, M, period, eb) < 1e-3 * eb else gsm.GSM_OK
+            assert _validate(g, po, [inst]) == want, (t, eb)
+            checked += want == gsm.GSM_E_SINGULAR
+    assert checked > 300  # the shell cases really hit the band
