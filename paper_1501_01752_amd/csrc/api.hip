@@ -116,6 +116,10 @@ struct gsm_plan_s {
   std::string arch;        // device architecture name, the cache's key
   // cached tuning results by (M, P, precision)
   std::map<std::array<int, 5>, std::array<int, 4>> tune_known;
+  // basis permittivities already resolved for an instance: key = the bytes
+  // of (wavelength, k_inc, M, requested eps_b); the result also depends only
+  // on the plan's periods and permittivity statistics
+  std::map<std::array<unsigned char, 60>, double> eps_b_known;
   long long graph_captures = 0, graph_launches = 0;
   unsigned long long graph_clock = 0;  // use counter for the graph caches
   bool graph_off = false;              // set if a capture ever fails: separate launches from then on
@@ -339,8 +343,21 @@ int build_systems(gsm_plan_s* plan, int n_inst, const gsm_instance* inst, const 
     int rc = check_instance(in, plan->mmax, i, !three_drives);
     if (rc) return rc;
     double eb;
-    rc = resolve_eps_b(plan->period, plan->eps_mean, plan->eps_min, plan->eps_max, in, i, &eb);
-    if (rc) return rc;
+    std::array<unsigned char, 60> key;
+    std::memcpy(key.data(), &in.wavelength, 8);
+    std::memcpy(key.data() + 8, in.k_inc, 24);
+    std::memcpy(key.data() + 32, in.M, 12);
+    std::memcpy(key.data() + 44, &in.eps_b, 8);
+    std::memset(key.data() + 52, 0, 8);
+    const auto known = plan->eps_b_known.find(key);
+    if (known != plan->eps_b_known.end()) {
+      eb = known->second;
+    } else {
+      rc = resolve_eps_b(plan->period, plan->eps_mean, plan->eps_min, plan->eps_max, in, i, &eb);
+      if (rc) return rc;
+      if (plan->eps_b_known.size() >= 65536) plan->eps_b_known.clear();
+      plan->eps_b_known[key] = eb;
+    }
     const int P = fft_size_for(in.M);
     if (P < 0) return fail(GSM_E_UNSUPPORTED, "instance %d: order count too large", i);
     const int nd = three_drives ? 3 : in.n_drive;

@@ -132,3 +132,19 @@ def test_basis_permittivity_on_the_light_cone_is_refused():
     with pytest.raises(gsm.GsmError) as e:
         plan.solve([inst], gsm.default_opts())
     assert e.value.status == gsm.GSM_E_SINGULAR
+    # refused again on a second call (a refusal is never remembered as a
+    # resolved basis permittivity), and the same instance with an admissible
+    # eps_b, then with the automatic choice, twice each: the plan remembers
+    # resolved values, which must not change a result
+    with pytest.raises(gsm.GsmError) as e:
+        plan.solve([inst], gsm.default_opts())
+    assert e.value.status == gsm.GSM_E_SINGULAR
+    for eb in (1.5, 0.0):
+        inst.eps_b = eb
+        say(f"eps_b request {eb}, two calls")
+        E1, info1, st1 = plan.solve([inst], gsm.default_opts(tol=1e-11))
+        E2, info2, st2 = plan.solve([inst], gsm.default_opts(tol=1e-11))
+        assert st1 == st2 == gsm.GSM_OK
+        assert info1[0]["eps_b"] == info2[0]["eps_b"] == (eb if eb > 0 else plan.basis_eps(inst))
+        import torch
+        assert torch.equal(E1, E2)
