@@ -148,3 +148,33 @@ def test_basis_permittivity_on_the_light_cone_is_refused():
         assert info1[0]["eps_b"] == info2[0]["eps_b"] == (eb if eb > 0 else plan.basis_eps(inst))
         import torch
         assert torch.equal(E1, E2)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_second_gram_schmidt_pass(precision):
+    """Homogeneous medium eps_h != eps_b: only the 3x3 block of the m = 0
+    harmonic is excited, so the Krylov space closes within the first steps
+    and the next w' is rounding noise, far below 1e-3 ||w||: that step takes
+    the second Gram-Schmidt pass.  A general drive at oblique incidence closes
+    it at the second step, a transverse drive at normal incidence (an
+    eigenvector) at the first, so in one batch the systems ask for the second
+    pass at different steps.  Every field must equal the dense LU solution."""
+    gsm = G()
+    M = (3, 3, 3)
+    lam = 1 / 0.3
+    eps = np.full((8, 8, 8), 2.5)
+    plan = gsm.Plan(eps, (1, 1, 1), M)
+    cases = [(k_vector(lam, (0.3, 0.4, 0.866)), (1, 0.5j, 0)), (k_vector(lam, (0, 0, 1)), (1, 0, 0))]
+    insts = [gsm.make_instance(lam, k, M, [a], eps_b=2.0) for k, a in cases]
+    prec = gsm.GSM_FP64 if precision == "fp64" else gsm.GSM_MIXED
+    say(f"homogeneous medium, second GS pass, {precision}")
+    E, info, st = plan.solve(insts, gsm.default_opts(tol=1e-12, precision=prec))
+    assert st == gsm.GSM_OK
+    assert sum(i["reorth"] for i in info) >= 1, info
+    E = E.cpu().numpy()
+    off = 0
+    for k, a in cases:
+        c, q = oracle_case(eps, (1, 1, 1), lam, k, M)
+        ref = O.solve_dense(c, M, q, 2.0, [np.array(a, complex)]).ravel()
+        assert rel_err(E[off:off + ref.size], ref) <= 1e-10
+        off += ref.size
