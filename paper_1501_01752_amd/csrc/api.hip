@@ -66,13 +66,14 @@ struct Grid {
   bool tuned[2] = {false, false};
 };
 
-// Fixed families when not tuned (measured at M = 15, P = 64): the whole
-// columns of the complex64 plane pass use the plain radix-4 codelets (the
-// fewest-operation ones spill there), and so does complex128 pass C.
+// Fixed families when not tuned (measured at M = 15, P = 64): the
+// fewest-operation codelets everywhere except complex128 pass C, which is
+// faster with the plain radix-4 ones.
 void default_families(int P, bool dbl, int* fam) {
+  (void)P;
   fam[0] = 0;
   fam[1] = 0;
-  fam[2] = (!dbl && P == 64) ? 1 : 0;
+  fam[2] = 0;
   fam[3] = dbl ? 1 : 0;
 }
 

@@ -105,5 +105,5 @@ def test_untuned_plan_uses_defaults():
     gsm = G()
     eps = inputs.sphere(16, 0.3, 4.0)
     plan = gsm.Plan(eps, (1, 1, 1), (15, 15, 15))
-    assert plan.tuning((15, 15, 15), gsm.GSM_MIXED) == ([0, 0, 1, 0], False)
+    assert plan.tuning((15, 15, 15), gsm.GSM_MIXED) == ([0, 0, 0, 0], False)
     assert plan.tuning((15, 15, 15), gsm.GSM_FP64) == ([0, 0, 0, 1], False)
