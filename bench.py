@@ -291,6 +291,21 @@ def kernel_table(prof):
             for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
 
+def matvec_hbm(prof):
+    """The complex64 matrix-vector product as a whole (passes A, B and C of
+    the profiled step): algorithmic bytes over the summed launch durations,
+    against the HBM peak."""
+    parts = [prof.get(f"pass_{x}_c64") for x in "abc"]
+    if not all(parts):
+        return None
+    ms = sum(v["ms"] for v in parts)
+    gbs = sum(v["bytes"] for v in parts) / (ms * 1e-3) / 1e9
+    return {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "launches": parts[0]["launches"], "ms": round(ms, 3),
+            "note": "passes A+B+C in complex64 over the extra step that times every class; pass B is "
+                    "vector-ALU bound, so the product stays below the HBM roofline"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -318,7 +333,9 @@ def main():
     # the dominant class
     gsm.profile_begin()
     run_step(gsm, bodies, opts)
-    kernels = kernel_table(gsm.profile_end())
+    prof_all = gsm.profile_end()
+    kernels = kernel_table(prof_all)
+    matvec = matvec_hbm(prof_all)
     dom_name = next(iter(kernels))
     dom_class = dom_name.rsplit("_", 1)[0]
 
@@ -399,6 +416,7 @@ def main():
                    "bodies": "concurrent (one host thread and stream each)" if args.concurrent_bodies else "serial",
                    "per_solve_mean": krylov},
         "roofline": roofline,
+        "matvec_hbm": matvec,
         "fp64_gpu_solve": fp64,
         "as_configured": as_configured,
         "uneven_sweep": sweep,
