@@ -79,6 +79,10 @@ OP_CASES = {
                    (12, 12, 12)),
     "sphere_m15": (lambda: inputs.sphere(64, 0.3, 4.0), (1, 1, 1), 1 / 0.3, (0, 0, 1), 1.0, (15, 15, 15)),
     "aniso_p128": (asym_body, (1.0, 0.9, 1.1), 1 / 0.4, (0.1, 0.2, 0.97), 1.0, (6, 5, 17)),
+    # P = 64 with different order counts per axis (rows and columns of the
+    # plane pass cropped differently, Mx < My and Mx > My)
+    "aniso_p64": (asym_body, (1.0, 0.9, 1.1), 1 / 0.35, (0.2, -0.3, 0.93), 1.0, (9, 14, 11)),
+    "aniso_p64b": (asym_body, (1.0, 0.9, 1.1), 1 / 0.35, (-0.4, 0.1, 0.91), 1.0, (15, 4, 9)),
 }
 
 
@@ -127,7 +131,7 @@ def test_apply_fp32(name):
         assert rel_err(y[d], ref) <= 3e-6, name
 
 
-@pytest.mark.parametrize("name", ["m1", "asym_m213", "sphere_m3", "aniso_p128"])
+@pytest.mark.parametrize("name", ["m1", "asym_m213", "sphere_m3", "aniso_p64", "aniso_p128"])
 def test_apply_adjoint(name):
     plan, inst, c, q, eb, M = _op_setup(name, ndrive=1)
     gsm = G()
