@@ -14,8 +14,8 @@
  *
  * with a restarted Krylov method (GMRES, the method the paper settles on in
  * its "Calculation details" section) whose matrix-vector product applies the
- * Toeplitz contrast matrix by FFT (the "heaviest procedure" of the truncation
- * section): inverse 3D FFT of the three field components, point-wise product
+ * Toeplitz contrast matrix by FFT (the step the truncation section singles out
+ * as the most costly): inverse 3D FFT of the three field components, point-wise product
  * with the band-limited contrast on the real-space grid, forward 3D FFT, then
  * the per-harmonic 3x3 Green tensor.  All of it runs in HIP kernels.
  *
@@ -36,6 +36,10 @@
  *   GSM_OUT_HOST flag says otherwise.  `stream` is a hipStream_t (NULL: the
  *   default stream).  Calls returning results synchronise that stream
  *   before they return.
+ * - The library is linked against the HIP runtime libamdhip64.so.7.  Device
+ *   pointers and streams passed in must belong to the runtime instance it is
+ *   bound to; in a process that also uses PyTorch, load PyTorch first (its
+ *   wheel carries its own copy of that runtime) so that the two share it.
  * - No call throws or aborts; every failure is a negative status and
  *   gsm_last_error() (thread-local) holds a message.  On error the outputs
  *   are left untouched, except GSM_W_* results, which are written.

@@ -179,7 +179,8 @@ def solve_dense(c, M, q, eps_b, drives):
 def contrast_convolution_fft(c, M, eps_b, x, P):
     """w_m = sum_m' (Delta eps / eps_b)_{m-m'} x_m' computed with FFTs.
 
-    The Toeplitz product by FFT named in the paper as the heaviest procedure:
+    The Toeplitz product by FFT, the step the paper singles out as the most
+    costly (section on the truncation):
     coefficients and field are placed on a P^3 grid at n mod P, taken to real
     space, multiplied point by point and taken back.  With P >= 4 M_a + 1 on
     every axis the cropped result equals the truncated Toeplitz product.

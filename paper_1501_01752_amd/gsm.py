@@ -105,9 +105,16 @@ _SIGS = {
 
 
 def lib():
-    """Load libgsm.so (raises if it has not been built)."""
+    """Load libgsm.so (raises if it has not been built).
+
+    PyTorch is imported first: its wheel carries its own HIP runtime
+    (libamdhip64.so.7), and the library must bind to that same runtime to
+    use torch's device memory and streams.  Loaded before torch, the library
+    would pull in the system's copy and torch would then fail to find a
+    device."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "python paper_1501_01752_amd/csrc/build.py")

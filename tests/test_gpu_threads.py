@@ -74,3 +74,27 @@ def test_two_plans_from_two_threads(profiled):
         assert torch.equal(E, alone[i]), i
     if profiled:
         assert stats["pass_b_c64"]["launches"] > 0 and stats["pass_b_c64"]["flops"] > 0
+
+
+def test_plan_before_any_torch_call():
+    """A fresh process that makes a plan and solves before it has touched
+    torch.cuda: the binding loads PyTorch's HIP runtime before the library,
+    so both use one runtime (otherwise torch would find no device)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import numpy as np\n"
+        "from paper_1501_01752_amd import gsm, inputs\n"
+        "w = inputs.sphere_lattice_small()\n"
+        "plan = gsm.Plan(w['eps'], w['period'], w['M'])\n"
+        "lam = w['wavelength']\n"
+        "inst = gsm.make_instance(lam, (0, 0, 2 * np.pi / lam), w['M'], [(1, 0, 0)])\n"
+        "E, info, st = plan.solve([inst])\n"
+        "print('ok', st, info[0]['rel_residual'])\n" % root)
+    say("fresh process: plan and solve before torch.cuda")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().startswith("ok 0"), r.stdout
