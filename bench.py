@@ -19,8 +19,10 @@ ones): its algorithmic bytes or flops over the durations of its launches in
 the timed steps, one launch in four bracketed by a hipEvent pair on its own
 stream (only that class carries events there); the per-class table of the
 extra step; the
-plain FP64 GPU solve of the same workload; and the CPU oracle (FFT + SciPy
-GMRES, FP64) timed on a bounded sample.
+plain FP64 GPU solve of the same workload; the literal 4-solve case, the
+uneven 256-instance sweep, the 32^3-voxel inverse-design gradient and the
+M = 31 woodpile batch as further lines of the same JSON object; and the CPU
+oracle (FFT + SciPy GMRES, FP64) timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -57,6 +59,10 @@ def parse():
     ap.add_argument("--sweep-steps", type=int, default=2,
                     help="steps of the uneven 256-instance sweep (0 skips it)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--design-steps", type=int, default=2,
+                    help="timed gradients of the 32^3-voxel inverse-design case (0: skip)")
+    ap.add_argument("--woodpile-steps", type=int, default=2,
+                    help="timed batched calls of the M = 31 woodpile case (0: skip)")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each complex64 Krylov cycle (library default if unset)")
     ap.add_argument("--concurrent-bodies", action="store_true",
@@ -291,6 +297,69 @@ def kernel_table(prof):
             for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
 
 
+def inverse_design(gsm, inputs, steps):
+    """Gradient of ||eps_eff - diag(4, 5, 6)||_F^2 with respect to the 32^3
+    voxel permittivities (Gaussian-smoothed seeded field stretched to
+    [1, 10], Lambda = 0.3 lambda, M = 12, normal incidence) through the
+    autograd function, as an optimisation loop would take it: each step
+    builds the plan of the current voxels, solves the three drives (forward)
+    and the three adjoint systems (backward), complex64 + FP64 refinement."""
+    import torch
+    eps0 = torch.tensor(inputs.smooth_random_field(32, seed=4), dtype=torch.float64, device="cuda:0")
+    lam, M = 1 / 0.3, (12, 12, 12)
+    inst = gsm.make_instance(lam, (0.0, 0.0, 2 * np.pi / lam), M)
+    target = torch.diag(torch.tensor([4.0, 5.0, 6.0], dtype=torch.complex128, device="cuda:0"))
+    fn = gsm.eff_tensor_fn()
+    opts = gsm.default_opts(tol=TOL)
+
+    def one():
+        e = eps0.clone().requires_grad_(True)
+        ee = fn.apply(e, (1.0, 1.0, 1.0), M, [inst], opts)
+        ((ee[0] - target).abs() ** 2).sum().backward()
+        return e.grad
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g = one()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": round(steps / dt, 3), "unit": "gradients/s", "ms_per_gradient": round(dt / steps * 1e3, 2),
+            "voxels": int(g.numel()), "orders": "25^3 (M = 12)",
+            "per_gradient": "plan build + 3 forward + 3 adjoint solves to 1e-9 + voxel correlation"}
+
+
+def woodpile(gsm, inputs, steps):
+    """Four-layer woodpile (rods of eps 10, 128^3 voxels), Lambda = 0.4
+    lambda, M = 31 (63^3 orders, 128^3 FFT grid), 16 seeded directions with a
+    transverse drive each in one batched call, complex64 + FP64 refinement to
+    1e-9."""
+    import torch
+    eps = inputs.woodpile(128, 10.0)
+    lam, M = 2.5, (31, 31, 31)
+    plan = gsm.Plan(eps, (1.0, 1.0, 1.0), M)
+    insts = []
+    for kh in inputs.random_directions(16, seed=5):
+        inst = gsm.make_instance(lam, 2 * np.pi / lam * np.asarray(kh), M, [tuple(inputs.transverse_drive(kh))])
+        inst.eps_b = plan.basis_eps(inst)
+        insts.append(inst)
+    opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30)
+    plan.solve(insts, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for _ in range(steps):
+        _, info, st = plan.solve(insts, opts)
+        if st != gsm.GSM_OK:
+            raise RuntimeError(f"woodpile solve status {st}")
+        worst = max(worst, max(i["rel_residual"] for i in info))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": round(16 * steps / dt, 3), "unit": "solves/s", "solves_per_step": 16,
+            "ms_per_step": round(dt / steps * 1e3, 1), "max_rel_residual": worst}
+
+
 def matvec_hbm(prof):
     """The complex64 matrix-vector product as a whole (passes A, B and C of
     the profiled step): algorithmic bytes over the summed launch durations,
@@ -398,6 +467,8 @@ def main():
                          "ms_per_step": round((t4 - t3) / args.config_steps * 1e3, 3)}
 
     sweep = uneven_sweep(gsm, inputs, args.sweep_steps, not args.no_autotune) if args.sweep_steps > 0 else None
+    design = inverse_design(gsm, inputs, args.design_steps) if args.design_steps > 0 else None
+    wood = woodpile(gsm, inputs, args.woodpile_steps) if args.woodpile_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     per_step = total // args.steps
     line = {
@@ -420,6 +491,8 @@ def main():
         "fp64_gpu_solve": fp64,
         "as_configured": as_configured,
         "uneven_sweep": sweep,
+        "inverse_design": design,
+        "woodpile": wood,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
