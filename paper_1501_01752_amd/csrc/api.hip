@@ -754,6 +754,7 @@ PassBytes pass_flops(const GroupShape& g) {
 
 template <typename T>
 int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step = -1) {
+  a.xnorm = (pa_mode & PA_NORMALIZE) ? 1 : 0;
   PassArgs<T> aa = a;
   aa.mode = pa_mode;
   const bool dbl = sizeof(T) == 8;

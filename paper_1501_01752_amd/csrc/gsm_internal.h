@@ -52,7 +52,7 @@ struct SysState {
   int pad[2];
   double rho;        // ||r|| of the last FP64 residual
   double rel;        // rho / bnorm
-  double vscale;     // factor applied to V[j] by the next pass A (normalisation)
+  double vscale;     // scale of the newest basis vector, applied as pass A reads it
   double inner_target;
   double xscale;     // factor applied to the Krylov correction (rho)
   double pad2;
@@ -67,6 +67,7 @@ struct SysState {
   double2 y[kMaxRestart];
   double2 hw[kMaxRestart + 2];   // first-pass Q^H w of the current step, then ||w||^2
   double2 hw2[kMaxRestart + 2];  // second-pass coefficients (when one is made)
+  double sigma[kMaxRestart + 1];  // the basis is stored unnormalised: q_k = sigma[k] V_k
 };
 
 // Shape of a group: systems sharing (M, P).
@@ -111,6 +112,7 @@ struct PassArgs {
   int gate;
   hipEvent_t ev0, ev1;  // when set: stamped at the start and end of the launch
   int fam[4];           // codelet family per stage: pass A, pass B rows, pass B columns, pass C
+  int xnorm;            // passes A and C read x scaled by the system's vscale
 };
 
 // ---- launchers (passes.hip) ----
