@@ -21,8 +21,9 @@ stream (only that class carries events there); the per-class table of the
 extra step; the
 plain FP64 GPU solve of the same workload; the literal 4-solve case, the
 uneven 256-instance sweep, the 32^3-voxel inverse-design gradient and the
-M = 31 woodpile batch as further lines of the same JSON object; and the CPU
-oracle (FFT + SciPy GMRES, FP64) timed on a bounded sample.
+M = 31 woodpile batch as further lines of the same JSON object; Table 1's
+single-solve workload at three sizes (context beside the paper's times); and
+the CPU oracle (FFT + SciPy GMRES, FP64) timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -63,6 +64,8 @@ def parse():
                     help="timed gradients of the 32^3-voxel inverse-design case (0: skip)")
     ap.add_argument("--woodpile-steps", type=int, default=2,
                     help="timed batched calls of the M = 31 woodpile case (0: skip)")
+    ap.add_argument("--table1-reps", type=int, default=10,
+                    help="timed single solves per size and precision of Table 1's workload (0: skip)")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="residual reduction asked of each complex64 Krylov cycle (library default if unset)")
     ap.add_argument("--concurrent-bodies", action="store_true",
@@ -360,6 +363,49 @@ def woodpile(gsm, inputs, steps):
             "ms_per_step": round(dt / steps * 1e3, 1), "max_rel_residual": worst}
 
 
+# Table 1 of the paper: GPU seconds per solve at 16^3, 32^3 and 64^3 harmonics
+# (FP64, 1e-8, its own GPU of 2013); context only, the nearest odd sizes here
+TABLE1_PAPER_GPU_S = {7: ("16^3", 0.166), 15: ("32^3", 0.244), 31: ("64^3", 0.448)}
+
+
+def table1(gsm, inputs, reps):
+    """Table 1's workload, one solve per call as in the table: spheres of
+    refractive index 3 in air (r = 0.3 Lambda, Lambda = 0.3 lambda), x drive at
+    normal incidence, GMRES(30) to a 1e-8 FP64 relative residual, in FP64 and
+    in complex64 + FP64 refinement, at 15^3, 31^3 and 63^3 harmonics.  Wall
+    time per call averaged over `reps` calls (the table averages ten), the plan
+    built beforehand.  The table's 128^3 and 256^3 rows need FFT sizes 256
+    and 512, beyond the built ones."""
+    import torch
+    rows = []
+    for M, (orders, paper_s) in TABLE1_PAPER_GPU_S.items():
+        w = inputs.sphere_lattice_table1(M)
+        lam = w["wavelength"]
+        k = 2 * np.pi / lam * np.asarray(w["k_hat"], dtype=np.float64)
+        plan = gsm.Plan(w["eps"], w["period"], w["M"])
+        inst = gsm.make_instance(lam, k, w["M"], w["drives"])
+        inst.eps_b = plan.basis_eps(inst)
+        row = {"harmonics": f"{2 * M + 1}^3", "M": M, "P": gsm.fft_size(w["M"]), "eps_b": inst.eps_b,
+               "paper_orders": orders, "paper_gpu_ms": paper_s * 1e3}
+        for name, prec in (("fp64", gsm.GSM_FP64), ("mixed", gsm.GSM_MIXED)):
+            opts = gsm.default_opts(tol=1e-8, precision=prec, restart=30)
+            plan.solve([inst], opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, info, st = plan.solve([inst], opts)
+                if st != gsm.GSM_OK:
+                    raise RuntimeError(f"Table 1 workload M={M} {name}: status {st}")
+            torch.cuda.synchronize()
+            row[f"{name}_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+            row[f"{name}_iterations"] = info[0]["iterations"]
+            row[f"{name}_rel_residual"] = info[0]["rel_residual"]
+        rows.append(row)
+        plan.close()
+    return {"unit": "ms per solve", "tol": 1e-8, "reps": reps, "rows": rows,
+            "note": "paper_gpu_ms: the paper's Table 1 (FP64, its 2013 GPU, 16/32/64 harmonics per axis), context"}
+
+
 def matvec_hbm(prof):
     """The complex64 matrix-vector product as a whole (passes A, B and C of
     the profiled step): algorithmic bytes over the summed launch durations,
@@ -469,6 +515,7 @@ def main():
     sweep = uneven_sweep(gsm, inputs, args.sweep_steps, not args.no_autotune) if args.sweep_steps > 0 else None
     design = inverse_design(gsm, inputs, args.design_steps) if args.design_steps > 0 else None
     wood = woodpile(gsm, inputs, args.woodpile_steps) if args.woodpile_steps > 0 else None
+    tab1 = table1(gsm, inputs, args.table1_reps) if args.table1_reps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     per_step = total // args.steps
     line = {
@@ -493,6 +540,7 @@ def main():
         "uneven_sweep": sweep,
         "inverse_design": design,
         "woodpile": wood,
+        "table1": tab1,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

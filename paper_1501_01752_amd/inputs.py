@@ -146,6 +146,16 @@ def sphere_lattice_m15():
                 drives=[(1.0, 0.0, 0.0), (0.0, 1.0, 0.0)])
 
 
+def sphere_lattice_table1(M):
+    """Table 1's workload: a cubic lattice of spheres of refractive index 3
+    (eps 9) in air.  The paper states neither the radius nor the period;
+    taken here as r = 0.3 Lambda and Lambda = 0.3 lambda, on 64^3 voxels;
+    normal incidence along z, x polarisation, M orders per axis (2M + 1
+    harmonics: 15, 31, 63 stand for the table's 16, 32, 64)."""
+    return dict(eps=sphere(64, 0.3, 9.0), period=(1.0, 1.0, 1.0), wavelength=1.0 / 0.3,
+                k_hat=(0.0, 0.0, 1.0), M=(M, M, M), drives=[(1.0, 0.0, 0.0)])
+
+
 def layered_stack_m15():
     """Stack f = 0.4, eps1 = 2.25, eps2 = 9 along z on 64 voxels, M = 15."""
     return dict(eps=layered_stack(64, 0.4, 2.25, 9.0), period=(1.0, 1.0, 1.0),

@@ -51,3 +51,21 @@ def to_torch(a):
 
 def rel_err(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def oracle_P(M):
+    """An FFT size per axis the oracle may use: any P >= 4M + 1 gives the same
+    operator; 2-3-5 smooth sizes keep numpy fast."""
+    out = []
+    for m in M:
+        p = 4 * m + 1
+        while True:
+            r = p
+            for f in (2, 3, 5):
+                while r % f == 0:
+                    r //= f
+            if r == 1:
+                break
+            p += 1
+        out.append(p)
+    return tuple(out)

@@ -14,7 +14,7 @@ and members of the batch equal the same instance solved alone.
 import numpy as np
 import pytest
 
-from gpu_common import k_vector, oracle_case, rel_err, say
+from gpu_common import k_vector, oracle_P, oracle_case, rel_err, say
 from oracle import gsm as O
 from paper_1501_01752_amd import inputs
 
@@ -33,24 +33,6 @@ def _need_gpu():
 def G():
     from paper_1501_01752_amd import gsm
     return gsm
-
-
-def _oracle_P(M):
-    """An FFT size per axis the oracle may use: any P >= 4M + 1 gives the same
-    operator; 2-3-5 smooth sizes keep numpy fast."""
-    out = []
-    for m in M:
-        p = 4 * m + 1
-        while True:
-            r = p
-            for f in (2, 3, 5):
-                while r % f == 0:
-                    r //= f
-            if r == 1:
-                break
-            p += 1
-        out.append(p)
-    return tuple(out)
 
 
 @pytest.fixture(scope="module")
@@ -103,7 +85,7 @@ def test_sweep_residual_by_oracle_operator(sweep):
         M, c, q, E = _member(sweep, i)
         say(f"oracle residual of sweep member {i} M={M[0]}")
         r = O.relative_residual(c, M, q, sweep["insts"][i].eps_b, sweep["drives"][i].astype(complex), E,
-                                _oracle_P(M))
+                                oracle_P(M))
         assert r <= 1e-10, (i, r)
 
 
@@ -114,7 +96,7 @@ def test_sweep_small_members_vs_oracle_solve(sweep):
         M, c, q, E = _member(sweep, i)
         say(f"oracle solve of sweep member {i} M=6")
         ref, _ = O.solve_fft_gmres(c, M, q, sweep["insts"][i].eps_b, sweep["drives"][i].astype(complex),
-                                   _oracle_P(M), rtol=1e-12)
+                                   oracle_P(M), rtol=1e-12)
         assert rel_err(E, ref) <= 1e-9
 
 
