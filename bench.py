@@ -64,6 +64,11 @@ def parse():
                     help="timed gradients of the 32^3-voxel inverse-design case (0: skip)")
     ap.add_argument("--woodpile-steps", type=int, default=2,
                     help="timed batched calls of the M = 31 woodpile case (0: skip)")
+    ap.add_argument("--group-max", type=int, default=None,
+                    help="systems per launch group (default: the library's, 32; 0: one group per call)")
+    ap.add_argument("--one-group-steps", type=int, default=None,
+                    help="timed steps with one launch group per call, for the dominant kernel's own rate "
+                         "(default: --steps; 0: skip)")
     ap.add_argument("--table1-reps", type=int, default=10,
                     help="timed single solves per size and precision of Table 1's workload (0: skip)")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -439,6 +444,8 @@ def main():
         matvec_only(gsm, work[0], args.matvec_only)
         return
     extra = {} if args.inner_tol is None else {"inner_tol": args.inner_tol}
+    if args.group_max is not None:
+        extra["group_max"] = args.group_max
     opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30, **extra)
     for _ in range(args.warmup):
         run_step(gsm, bodies, opts)
@@ -473,11 +480,46 @@ def main():
     value = total / dt
     # roofline of the dominant class from its launches in the timed steps
     roofline = roofline_of(dom_name, prof[dom_name])
+    roofline["group_max"] = opts.group_max
     rec = counted_traffic(dom_name)
-    if rec is not None:
-        roofline["traffic"] = rec["traffic_bytes_per_dispatch"]
-        roofline["traffic_algorithmic"] = rec["algorithmic_bytes_per_dispatch"]
-        roofline["traffic_launch"] = rec["launch"]
+
+    def add_traffic(r):
+        r["traffic"] = rec["traffic_bytes_per_dispatch"]
+        r["traffic_algorithmic"] = rec["algorithmic_bytes_per_dispatch"]
+        r["traffic_launch"] = rec["launch"]
+
+    if opts.group_max != 0:
+        roofline["note"] = ("the systems of a call run as concurrent launch groups of at most group_max: a "
+                            "launch's event duration includes the other groups' concurrent work, so this rate "
+                            "is a lower bound of the kernel's own; roofline_one_group times it alone")
+    elif rec is not None:
+        add_traffic(roofline)
+
+    # the same steps with one launch group per call (no concurrent groups):
+    # the dominant kernel's own launch rate, and the throughput without
+    # splitting, timed on their own
+    one_group = None
+    og_steps = args.steps if args.one_group_steps is None else args.one_group_steps
+    if og_steps > 0 and opts.group_max != 0:
+        opts1 = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30,
+                                 **{k: v for k, v in extra.items() if k != "group_max"}, group_max=0)
+        run_step(gsm, bodies, opts1)
+        gsm.profile_begin(only=dom_class, every=args.profile_every)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        n1 = 0
+        for _ in range(og_steps):
+            n, _ = run_step(gsm, bodies, opts1)
+            n1 += n
+        torch.cuda.synchronize()
+        t6 = time.perf_counter()
+        prof1 = gsm.profile_end()
+        one_group = roofline_of(dom_name, prof1[dom_name])
+        one_group["group_max"] = 0
+        one_group["solves_per_s"] = round(n1 / (t6 - t5), 3)
+        one_group["steps"] = og_steps
+        if rec is not None:
+            add_traffic(one_group)
 
     # plain FP64 GPU solve of the same workload
     fp64 = None
@@ -532,8 +574,10 @@ def main():
                    "codelet_families": {name: work[i][0].tuning(work[i][1][0].M)[0]
                                         for i, name in enumerate(("sphere", "stack"))},
                    "bodies": "concurrent (one host thread and stream each)" if args.concurrent_bodies else "serial",
+                   "group_max": opts.group_max,
                    "per_solve_mean": krylov},
         "roofline": roofline,
+        "roofline_one_group": one_group,
         "matvec_hbm": matvec,
         "fp64_gpu_solve": fp64,
         "as_configured": as_configured,

@@ -144,6 +144,14 @@ typedef struct gsm_solver_opts {
   int32_t method;     /* GSM_GMRES or GSM_BICGSTAB */
   int32_t flags;      /* GSM_OUT_HOST */
   const double* x0;   /* NULL or an initial guess (device, layout of E_out) */
+  int32_t group_max;  /* systems per launch group, >= 0 (0: no limit); default 32.
+                         The systems of a call that share (M, P) are split into
+                         groups of at most this many, which the scheduler runs
+                         concurrently on its streams, so that the last steps of
+                         one group's Krylov cycles, when few of its systems still
+                         work, overlap with another group's launches.  The
+                         workspace query must be given the same value. */
+  int32_t reserved;   /* set to 0 */
 } gsm_solver_opts;
 
 /* Result of one system (instance, drive). */

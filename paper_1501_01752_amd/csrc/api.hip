@@ -192,6 +192,8 @@ int check_solver_opts(const gsm_solver_opts* s) {
   if (s->method == GSM_BICGSTAB && s->restart < 5)
     return fail(GSM_E_ARG, "BiCGStab keeps six vectors per system: restart must be >= 5");
   if (s->flags & ~(GSM_OUT_HOST | GSM_SOLVE_GRAPH)) return fail(GSM_E_ARG, "unknown solver flags");
+  if (s->group_max < 0) return fail(GSM_E_ARG, "group_max must be >= 0");
+  if (s->reserved != 0) return fail(GSM_E_ARG, "reserved solver field must be 0");
   return GSM_OK;
 }
 
@@ -405,14 +407,16 @@ int build_systems(gsm_plan_s* plan, int n_inst, const gsm_instance* inst, const 
   return GSM_OK;
 }
 
-void build_groups(const std::vector<SysDesc>& sys, std::vector<Group>& groups) {
+// Systems sharing (M, P) form a group, split into groups of at most
+// group_max systems (0: no limit).
+void build_groups(const std::vector<SysDesc>& sys, std::vector<Group>& groups, int group_max) {
   groups.clear();
   std::map<std::array<int, 4>, int> key2g;
   for (int i = 0; i < (int)sys.size(); ++i) {
     const SysDesc& s = sys[i];
     std::array<int, 4> key{s.M[0], s.M[1], s.M[2], s.P};
     auto it = key2g.find(key);
-    if (it == key2g.end()) {
+    if (it == key2g.end() || (group_max > 0 && (int)groups[it->second].sys.size() >= group_max)) {
       Group g;
       GroupShape& sh = g.shape;
       for (int a = 0; a < 3; ++a) {
@@ -1425,6 +1429,7 @@ void gsm_solver_opts_default(gsm_solver_opts* o) {
   o->method = GSM_GMRES;
   o->flags = 0;
   o->x0 = nullptr;
+  o->group_max = 32;
 }
 
 int gsm_fft_size(const int32_t M[3]) {
@@ -1654,7 +1659,7 @@ int gsm_workspace_size(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
   std::vector<SysDesc> sys3;
   if ((rc = build_systems(p, n_inst, inst, so, true, sys3))) return rc;
   std::vector<Group> groups;
-  build_groups(sys3, groups);
+  build_groups(sys3, groups, so->group_max);
   *bytes = workspace_for(groups, so->restart, so->precision == GSM_FP64);
   return GSM_OK;
 }
@@ -1668,7 +1673,7 @@ int gsm_solve(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const gsm_
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, so, false, sys))) return rc;
   std::vector<Group> groups;
-  build_groups(sys, groups);
+  build_groups(sys, groups, so->group_max);
   hipStream_t st = (hipStream_t)stream;
   std::vector<SysExport> exp;
   rc = solve_all(p, sys, groups, so, ws, ws_bytes, E_out, (so->flags & GSM_OUT_HOST) != 0, exp, st);
@@ -1691,7 +1696,7 @@ int gsm_apply(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t pr
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, &so, false, sys))) return rc;
   std::vector<Group> groups;
-  build_groups(sys, groups);
+  build_groups(sys, groups, 0);  // one pass: nothing to overlap, and never more groups than the workspace query
   if ((rc = carve(groups, ws, ws_bytes, so.restart, precision == GSM_FP64))) return rc;
   hipStream_t st = (hipStream_t)stream;
   const bool dbl = precision == GSM_FP64;
@@ -1749,7 +1754,7 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, so, true, sys))) return rc;
   std::vector<Group> groups;
-  build_groups(sys, groups);
+  build_groups(sys, groups, so->group_max);
   hipStream_t st = (hipStream_t)stream;
   long long total = 0;
   for (auto& s : sys) total += s.n;
@@ -1867,7 +1872,7 @@ int gsm_solve_adjoint(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, co
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, so, false, sys))) return rc;
   std::vector<Group> groups;
-  build_groups(sys, groups);
+  build_groups(sys, groups, so->group_max);
   std::vector<SysExport> exp;
   rc = solve_all(p, sys, groups, so, ws, ws_bytes, lambda_out, (so->flags & GSM_OUT_HOST) != 0, exp,
                  (hipStream_t)stream, rhs);
@@ -1915,7 +1920,7 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, so, true, sys))) return rc;
   std::vector<Group> groups;
-  build_groups(sys, groups);
+  build_groups(sys, groups, so->group_max);
   long long total = 0;
   for (auto& s : sys) total += s.n;
   double2 *rhs = nullptr, *lam = nullptr;

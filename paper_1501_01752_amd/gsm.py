@@ -40,7 +40,8 @@ class Instance(C.Structure):
 class SolverOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("max_refine", C.c_int32), ("precision", C.c_int32),
-                ("method", C.c_int32), ("flags", C.c_int32), ("x0", C.c_void_p)]
+                ("method", C.c_int32), ("flags", C.c_int32), ("x0", C.c_void_p),
+                ("group_max", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
