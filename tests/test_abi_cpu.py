@@ -31,6 +31,21 @@ def test_binding_covers_declared_symbols():
     assert set(_declared()) <= set(gsm._SIGS)
 
 
+def test_solver_opts_layout_matches_the_library():
+    """The library's defaults fill exactly the binding's struct: a buffer of
+    sentinel bytes larger than the struct keeps its tail, and every field
+    reads back the documented default where the binding expects it."""
+    L = gsm.lib()
+    size = C.sizeof(gsm.SolverOpts)
+    buf = (C.c_ubyte * (size + 64))(*([0xA5] * (size + 64)))
+    L.gsm_solver_opts_default(C.cast(buf, C.POINTER(gsm.SolverOpts)))
+    assert bytes(buf[size:]) == b"\xa5" * 64
+    o = gsm.SolverOpts.from_buffer_copy(bytes(buf[:size]))
+    assert (o.tol, o.inner_tol, o.restart, o.max_iter, o.max_refine) == (1e-9, 1e-5, 30, 5000, 200)
+    assert (o.precision, o.method, o.flags) == (gsm.GSM_MIXED, gsm.GSM_GMRES, 0)
+    assert not o.x0 and o.group_max == 32 and o.reserved == 0
+
+
 def test_strerror_and_defaults():
     L = gsm.lib()
     assert L.gsm_strerror(gsm.GSM_E_SINGULAR)
