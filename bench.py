@@ -75,9 +75,10 @@ def parse():
                     help="residual reduction asked of each complex64 Krylov cycle (library default if unset)")
     ap.add_argument("--concurrent-bodies", action="store_true",
                     help="solve the two bodies of a step concurrently, one host thread and stream each "
-                         "(measured about 5%% fewer solves/s than one after the other; the launches of the "
-                         "two streams share the GPU, so the timed launch durations of the roofline include "
-                         "the other stream's work); default: one after the other")
+                         "(with launch groups of 32 about 4%% more solves/s than one after the other; the "
+                         "launches of the streams share the GPU, so the timed launch durations of the "
+                         "roofline include the other streams' work and drift further from the profiler's "
+                         "kernel durations); default: one after the other")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed codelet families instead of timing them at the first solve")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="REPS",
