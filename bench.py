@@ -81,6 +81,8 @@ def parse():
                          "kernel durations); default: one after the other")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed codelet families instead of timing them at the first solve")
+    ap.add_argument("--matvec-systems", type=int, default=0,
+                    help="with --matvec-only: apply the operator to the first N systems of the body (0: all)")
     ap.add_argument("--matvec-only", type=int, default=0, metavar="REPS",
                     help="for hardware-counter runs: a 1 GiB device copy (calibration), then REPS "
                          "batched operator applications of one body of the step in complex64 and "
@@ -226,10 +228,17 @@ def cpu_baseline(inputs):
                       f"FP64 numpy FFT + scipy GMRES(30) to 1e-9), {its} iterations, {wall:.1f} s wall"}
 
 
-def matvec_only(gsm, body, reps):
-    """Copy calibration and bare operator applications (no solve)."""
+def matvec_only(gsm, body, reps, systems=0):
+    """Copy calibration and bare operator applications (no solve), of the
+    first `systems` systems of the body (0: all)."""
     import torch
     plan, insts = body
+    if systems > 0:
+        sizes = [len(gsm.system_sizes([i])) for i in insts]
+        keep = int(np.searchsorted(np.cumsum(sizes), systems)) + 1
+        insts = insts[:keep]
+        if len(gsm.system_sizes(insts)) != systems:
+            raise ValueError(f"no instance prefix of the body holds exactly {systems} systems")
     out = {}
     # a plain shader copy of 1 GiB (read 1 GiB, write 1 GiB): torch's
     # elementwise negation of 2^28 float32 values
@@ -280,12 +289,13 @@ def roofline_of(name, v):
             "frac": round(gbs / HBM_PEAK_GBS, 4), **common}
 
 
-def counted_traffic(name):
-    """HBM bytes per launch of kernel class `name` from the committed
-    hardware-counter record (FETCH_SIZE / WRITE_SIZE scaled by a copy-kernel
-    calibration), or None when there is none or the kernel sources changed
-    since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{name}_m15_counters.json")
+def counted_traffic(name, systems=64):
+    """HBM bytes per launch of kernel class `name` over `systems` systems from
+    the committed hardware-counter record (FETCH_SIZE / WRITE_SIZE scaled by a
+    copy-kernel calibration), or None when there is none or the kernel
+    sources changed since it was taken."""
+    tag = "" if systems == 64 else f"_{systems}sys"
+    path = os.path.join(ROOT, "profiles", f"{name}_m15{tag}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -442,7 +452,7 @@ def main():
     work = build_workload(gsm, inputs, args.directions, autotune=not args.no_autotune)
     bodies = Bodies(work, serial=not args.concurrent_bodies)
     if args.matvec_only:
-        matvec_only(gsm, work[0], args.matvec_only)
+        matvec_only(gsm, work[0], args.matvec_only, args.matvec_systems)
         return
     extra = {} if args.inner_tol is None else {"inner_tol": args.inner_tol}
     if args.group_max is not None:
@@ -484,17 +494,20 @@ def main():
     roofline["group_max"] = opts.group_max
     rec = counted_traffic(dom_name)
 
-    def add_traffic(r):
-        r["traffic"] = rec["traffic_bytes_per_dispatch"]
-        r["traffic_algorithmic"] = rec["algorithmic_bytes_per_dispatch"]
-        r["traffic_launch"] = rec["launch"]
+    def add_traffic(r, record):
+        r["traffic"] = record["traffic_bytes_per_dispatch"]
+        r["traffic_algorithmic"] = record["algorithmic_bytes_per_dispatch"]
+        r["traffic_launch"] = record["launch"]
 
+    # counters taken on a launch of as many systems as the timed launches carry
+    per_launch = min(opts.group_max or 10 ** 9, len(gsm.system_sizes(work[0][1])))
+    rec_launch = counted_traffic(dom_name, per_launch)
+    if rec_launch is not None:
+        add_traffic(roofline, rec_launch)
     if opts.group_max != 0:
         roofline["note"] = ("the systems of a call run as concurrent launch groups of at most group_max: a "
                             "launch's event duration includes the other groups' concurrent work, so this rate "
                             "is a lower bound of the kernel's own; roofline_one_group times it alone")
-    elif rec is not None:
-        add_traffic(roofline)
 
     # the same steps with one launch group per call (no concurrent groups):
     # the dominant kernel's own launch rate, and the throughput without
@@ -520,7 +533,7 @@ def main():
         one_group["solves_per_s"] = round(n1 / (t6 - t5), 3)
         one_group["steps"] = og_steps
         if rec is not None:
-            add_traffic(one_group)
+            add_traffic(one_group, rec)
 
     # plain FP64 GPU solve of the same workload
     fp64 = None
