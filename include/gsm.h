@@ -215,9 +215,16 @@ int gsm_plan_contrast_grid(gsm_plan_t plan, const int32_t M[3], int32_t P, doubl
 
 /* ------------------------------------------------------------- workspace */
 
-/* Bytes of device workspace gsm_solve / gsm_eff_tensor / gsm_apply need for
- * these instances and options (the caller allocates it, e.g. as a torch
- * uint8 tensor, and may reuse it across calls). */
+/* Bytes of device workspace gsm_solve, gsm_apply, gsm_solve_adjoint,
+ * gsm_eff_tensor and gsm_eff_tensor_vjp need for these instances and options
+ * (the caller allocates it, e.g. as a torch uint8 tensor, and may reuse it
+ * across calls).  The size covers three drives per instance and the
+ * effective-tensor calls' own buffers (solved fields, adjoint right-hand
+ * sides and solutions, the correlation grids of the gradient), so none of
+ * these calls allocates device memory for its arithmetic.  Plan state is
+ * allocated on first need and then kept: the real-space contrast grids of a
+ * new (M, P), and the scheduler's pinned host words when a call has more
+ * systems than any before (see gsm_allocation_stats). */
 int gsm_workspace_size(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
                        const gsm_solver_opts* opts, size_t* bytes);
 
@@ -276,6 +283,12 @@ int gsm_eff_tensor_vjp(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst
  * instantiated, *launched = graph launches (each runs a few Krylov steps of
  * one group).  Either pointer may be NULL.  GSM_E_ARG for a NULL plan. */
 int gsm_plan_graph_stats(gsm_plan_t plan, int64_t* captured, int64_t* launched);
+
+/* Allocations the library has made since it was loaded: *count calls and
+ * *bytes in total of hipMalloc (device) and hipHostMalloc (pinned host).
+ * Either pointer may be NULL.  Repeated calls on a plan whose contrast grids
+ * and pinned words exist leave both unchanged. */
+int gsm_allocation_stats(int64_t* count, int64_t* bytes);
 
 /* Codelet families (0: fewest operations, 1: plain radix 4) used for the
  * orders M with the precision given, per FFT stage: fam[0] pass A (z),

@@ -6,13 +6,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -56,6 +56,29 @@ int fft_size_for(const int32_t M[3]) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Every device (hipMalloc) and pinned host (hipHostMalloc) allocation of the
+// library goes through these, so that gsm_allocation_stats can show which
+// calls allocate: plan set-up, the first use of an (M, P) grid and slot
+// buffers do; repeated solves on a plan do not.
+std::atomic<long long> g_alloc_count{0}, g_alloc_bytes{0};
+hipError_t dev_malloc(void** p, size_t bytes) {
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) {
+    ++g_alloc_count;
+    g_alloc_bytes += (long long)bytes;
+  }
+  return e;
+}
+template <typename T> hipError_t dev_malloc(T** p, size_t bytes) { return dev_malloc((void**)p, bytes); }
+hipError_t pinned_malloc(void** p, size_t bytes) {
+  const hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    ++g_alloc_count;
+    g_alloc_bytes += (long long)bytes;
+  }
+  return e;
+}
 
 struct Grid {
   double* g64 = nullptr;
@@ -493,6 +516,72 @@ int carve(std::vector<Group>& groups, void* ws, size_t ws_bytes, int restart, bo
   return GSM_OK;
 }
 
+// ----------------------------------------------- effective-tensor region --
+// Workspace of gsm_eff_tensor and gsm_eff_tensor_vjp beyond the groups'
+// solve buffers: two field arrays over the three-drive systems of the call
+// (the solved fields when the caller keeps none; the adjoint right-hand sides
+// and solutions), and the correlation buffers of one instance at a time
+// (sized for the largest): two DFT staging arrays, the two expanded fields,
+// the real-space product on the P^3 grid, the |n| <= 2M coefficients and the
+// voxel-space result.
+enum { AUX_T1, AUX_T2, AUX_AH, AUX_EH, AUX_Y, AUX_X, AUX_GV, AUX_NTMP };
+
+void vjp_tmp_counts(const gsm_plan_s* plan, const SysDesc& s0, long long cnt[AUX_NTMP]) {
+  const long long P = s0.P, P3 = P * P * P;
+  const long long N1[3] = {2LL * s0.M[0] + 1, 2LL * s0.M[1] + 1, 2LL * s0.M[2] + 1};
+  const long long nc[3] = {4LL * s0.M[0] + 1, 4LL * s0.M[1] + 1, 4LL * s0.M[2] + 1};
+  const long long ncn = nc[0] * nc[1] * nc[2];
+  const long long nvox = (long long)plan->vox[0] * plan->vox[1] * plan->vox[2];
+  const long long tsz = std::max<long long>({P3, N1[2] * N1[1] * P, N1[2] * P * P, P * P * nc[0], P * nc[1] * nc[0],
+                                             nc[2] * nc[1] * plan->vox[0], nc[2] * plan->vox[1] * plan->vox[0]});
+  cnt[AUX_T1] = cnt[AUX_T2] = tsz;
+  cnt[AUX_AH] = cnt[AUX_EH] = cnt[AUX_Y] = P3;
+  cnt[AUX_X] = ncn;
+  cnt[AUX_GV] = std::max(nvox, ncn);
+}
+
+struct Aux {
+  double2* f[2] = {nullptr, nullptr};
+  double2* tmp[AUX_NTMP] = {};
+};
+
+// Bytes of the region for three-drive systems `sys` (base == nullptr: size only).
+size_t aux_layout(const gsm_plan_s* plan, const std::vector<SysDesc>& sys, char* base, Aux* out) {
+  long long total = 0;
+  for (auto& s : sys) total += s.n;
+  size_t off = 0;
+  auto take = [&](long long count) {
+    double2* q = base ? (double2*)(base + off) : nullptr;
+    off += align256((size_t)std::max<long long>(count, 1) * sizeof(double2));
+    return q;
+  };
+  Aux a;
+  a.f[0] = take(total);
+  a.f[1] = take(total);
+  long long cmax[AUX_NTMP] = {};
+  for (size_t i = 0; i < sys.size(); i += 3) {
+    long long c[AUX_NTMP];
+    vjp_tmp_counts(plan, sys[i], c);
+    for (int k = 0; k < AUX_NTMP; ++k) cmax[k] = std::max(cmax[k], c[k]);
+  }
+  for (int k = 0; k < AUX_NTMP; ++k) a.tmp[k] = take(cmax[k]);
+  if (out) *out = a;
+  return off;
+}
+
+// The region follows the groups' buffers in the caller's workspace.
+int carve_aux(const gsm_plan_s* plan, std::vector<Group>& groups, const std::vector<SysDesc>& sys, void* ws,
+              size_t ws_bytes, int restart, bool fp64, Aux* out) {
+  const size_t gbytes = workspace_for(groups, restart, fp64);
+  const size_t need = gbytes + aux_layout(plan, sys, nullptr, nullptr);
+  if (!ws) return fail(GSM_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(GSM_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  // gbytes holds 256 bytes of slack for aligning the start of the groups
+  char* p = (char*)(((uintptr_t)ws + 255) & ~uintptr_t(255)) + (gbytes - 256);
+  aux_layout(plan, sys, p, out);
+  return GSM_OK;
+}
+
 // ------------------------------------------------------------ plan grids --
 
 int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** out) {
@@ -507,11 +596,11 @@ int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** 
   const int nb[3] = {4 * M[0] + 1, 4 * M[1] + 1, 4 * M[2] + 1};
   const long long nbt = (long long)nb[0] * nb[1] * nb[2];
   double2 *blk = nullptr, *t1 = nullptr, *t2 = nullptr;
-  HIP_TRY(hipMalloc(&g.g64, P3 * sizeof(double)));
-  HIP_TRY(hipMalloc(&g.g32, P3 * sizeof(float)));
-  HIP_TRY(hipMalloc(&blk, nbt * sizeof(double2)));
-  HIP_TRY(hipMalloc(&t1, std::max((long long)P * nb[1] * nb[2], P3) * sizeof(double2)));
-  HIP_TRY(hipMalloc(&t2, P3 * sizeof(double2)));
+  HIP_TRY(dev_malloc(&g.g64, P3 * sizeof(double)));
+  HIP_TRY(dev_malloc(&g.g32, P3 * sizeof(float)));
+  HIP_TRY(dev_malloc(&blk, nbt * sizeof(double2)));
+  HIP_TRY(dev_malloc(&t1, std::max((long long)P * nb[1] * nb[2], P3) * sizeof(double2)));
+  HIP_TRY(dev_malloc(&t2, P3 * sizeof(double2)));
   const int off[3] = {2 * plan->mmax[0] - 2 * M[0], 2 * plan->mmax[1] - 2 * M[1], 2 * plan->mmax[2] - 2 * M[2]};
   HIP_TRY(launch_copy_block(plan->d_coef, blk, plan->nc, nb, off, st));
   // x: blk[nz][ny][nbx] -> t1[nz][ny][P]
@@ -553,9 +642,9 @@ int ensure_slot(gsm_plan_s* plan, int k, int S, size_t exp_bytes) {
   sl.h_exp = nullptr;
   sl.cap = 0;
   const int cap = std::max(S, 64);
-  HIP_TRY(hipHostMalloc((void**)&sl.h_flags, 2 * cap * sizeof(int), hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc((void**)&sl.h_inner, cap * sizeof(int), hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc(&sl.h_exp, cap * exp_bytes, hipHostMallocDefault));
+  HIP_TRY(pinned_malloc((void**)&sl.h_flags, 2 * cap * sizeof(int)));
+  HIP_TRY(pinned_malloc((void**)&sl.h_inner, cap * sizeof(int)));
+  HIP_TRY(pinned_malloc(&sl.h_exp, cap * exp_bytes));
   sl.cap = cap;
   return GSM_OK;
 }
@@ -1521,10 +1610,10 @@ int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out
   const long long ncx = p->nc[0], ncy = p->nc[1], ncz = p->nc[2];
   const long long na = std::max(nv, (long long)p->vox[2] * ncy * ncx);
   const long long nb = (long long)p->vox[2] * p->vox[1] * ncx;
-  hipError_t e = hipMalloc(&d_eps, nv * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&a, na * sizeof(double2));
-  if (e == hipSuccess) e = hipMalloc(&b, nb * sizeof(double2));
-  if (e == hipSuccess) e = hipMalloc(&p->d_coef, ncx * ncy * ncz * sizeof(double2));
+  hipError_t e = dev_malloc(&d_eps, nv * sizeof(double));
+  if (e == hipSuccess) e = dev_malloc(&a, na * sizeof(double2));
+  if (e == hipSuccess) e = dev_malloc(&b, nb * sizeof(double2));
+  if (e == hipSuccess) e = dev_malloc(&p->d_coef, ncx * ncy * ncz * sizeof(double2));
   if (e != hipSuccess) {
     hipFree(d_eps);
     hipFree(a);
@@ -1581,6 +1670,12 @@ int gsm_plan_graph_stats(gsm_plan_t p, int64_t* captured, int64_t* launched) {
   if (!p) return fail(GSM_E_ARG, "NULL plan");
   if (captured) *captured = p->graph_captures;
   if (launched) *launched = p->graph_launches;
+  return GSM_OK;
+}
+
+int gsm_allocation_stats(int64_t* count, int64_t* bytes) {
+  if (count) *count = g_alloc_count.load();
+  if (bytes) *bytes = g_alloc_bytes.load();
   return GSM_OK;
 }
 
@@ -1660,7 +1755,9 @@ int gsm_workspace_size(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
   if ((rc = build_systems(p, n_inst, inst, so, true, sys3))) return rc;
   std::vector<Group> groups;
   build_groups(sys3, groups, so->group_max);
-  *bytes = workspace_for(groups, so->restart, so->precision == GSM_FP64);
+  // plus the effective-tensor region (fields and correlation buffers), so
+  // that no call on the workspace allocates device memory of its own
+  *bytes = workspace_for(groups, so->restart, so->precision == GSM_FP64) + aux_layout(p, sys3, nullptr, nullptr);
   return GSM_OK;
 }
 
@@ -1756,19 +1853,14 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
   std::vector<Group> groups;
   build_groups(sys, groups, so->group_max);
   hipStream_t st = (hipStream_t)stream;
-  long long total = 0;
-  for (auto& s : sys) total += s.n;
-  double* E = E_save;
-  double* tmp = nullptr;
-  if (!E) {
-    HIP_TRY(hipMalloc(&tmp, std::max<long long>(1, total) * sizeof(double2)));
-    E = tmp;
-  }
+  Aux ax;
+  if ((rc = carve_aux(p, groups, sys, ws, ws_bytes, so->restart, so->precision == GSM_FP64, &ax))) return rc;
+  // the fields go to the caller's E_save, else to the workspace
+  double* E = E_save ? E_save : (double*)ax.f[0];
   std::vector<SysExport> exp;
   gsm_solver_opts so2 = *so;
   so2.flags &= ~GSM_OUT_HOST;
   rc = solve_all(p, sys, groups, &so2, ws, ws_bytes, E, false, exp, st);
-  if (tmp) hipFree(tmp);
   if (rc) return rc;
   int worst = GSM_OK;
   fill_info(sys, exp, info, &worst);
@@ -1921,17 +2013,12 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
   if ((rc = build_systems(p, n_inst, inst, so, true, sys))) return rc;
   std::vector<Group> groups;
   build_groups(sys, groups, so->group_max);
-  long long total = 0;
-  for (auto& s : sys) total += s.n;
-  double2 *rhs = nullptr, *lam = nullptr;
-  HIP_TRY(hipMalloc(&rhs, total * sizeof(double2)));
-  HIP_TRY(hipMalloc(&lam, total * sizeof(double2)));
+  // right-hand sides, adjoint solutions and correlation buffers: workspace
+  Aux ax;
+  if ((rc = carve_aux(p, groups, sys, ws, ws_bytes, so->restart, so->precision == GSM_FP64, &ax))) return rc;
+  double2* rhs = ax.f[0];
+  double2* lam = ax.f[1];
   std::vector<AdjInst> ais(n_inst);
-  auto cleanup = [&](int code) {
-    hipFree(rhs);
-    hipFree(lam);
-    return code;
-  };
   const double2* E = (const double2*)E_save;
   for (int i = 0; i < n_inst; ++i) {
     const SysDesc& s0 = sys[3 * i];
@@ -1942,7 +2029,7 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
       for (int a = 0; a < 3; ++a) {
         double2 v;
         if (hipMemcpy(&v, E + sys[3 * i + d].out_off + a * N + i0, sizeof v, hipMemcpyDeviceToHost) != hipSuccess)
-          return cleanup(fail(GSM_E_DEVICE, "reading the saved fields failed"));
+          return fail(GSM_E_DEVICE, "reading the saved fields failed");
         E0[a][d] = cplxd(v.x, v.y);
       }
     for (int r = 0; r < 3; ++r)
@@ -1951,7 +2038,7 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
         gb[r][c] = cplxd(gbar[(9 * i + 3 * r + c) * 2], gbar[(9 * i + 3 * r + c) * 2 + 1]);
       }
     inv3(E0, E0inv, &det);
-    if (!(std::abs(det) > 0)) return cleanup(fail(GSM_E_SINGULAR, "instance %d: E0 is singular", i));
+    if (!(std::abs(det) > 0)) return fail(GSM_E_SINGULAR, "instance %d: E0 is singular", i);
     AdjInst& ai = ais[i];
     std::memset(&ai, 0, sizeof ai);
     for (int a = 0; a < 3; ++a) {
@@ -1978,11 +2065,11 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
       }
     }
     if (hipSuccess != launch_adjoint_rhs(p->d_coef, ai, rhs + s0.out_off, st))
-      return cleanup(fail(GSM_E_DEVICE, "adjoint right-hand side launch failed"));
+      return fail(GSM_E_DEVICE, "adjoint right-hand side launch failed");
   }
   std::vector<SysExport> exp;
   rc = solve_all(p, sys, groups, so, ws, ws_bytes, (double*)lam, false, exp, st, (const double*)rhs);
-  if (rc) return cleanup(rc);
+  if (rc) return rc;
   const long long nvox = (long long)p->vox[0] * p->vox[1] * p->vox[2];
   for (int i = 0; i < n_inst; ++i) {
     const SysDesc& s0 = sys[3 * i];
@@ -1991,20 +2078,9 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
     const long long P3 = (long long)P * P * P;
     const long long N = s0.n / 3;
     const int nc[3] = {4 * ai.M[0] + 1, 4 * ai.M[1] + 1, 4 * ai.M[2] + 1};
-    const long long ncn = (long long)nc[0] * nc[1] * nc[2];
-    double2 *t1 = nullptr, *t2 = nullptr, *ah = nullptr, *eh = nullptr, *Y = nullptr, *X = nullptr, *gv = nullptr;
+    double2 *t1 = ax.tmp[AUX_T1], *t2 = ax.tmp[AUX_T2], *ah = ax.tmp[AUX_AH], *eh = ax.tmp[AUX_EH];
+    double2 *Y = ax.tmp[AUX_Y], *X = ax.tmp[AUX_X], *gv = ax.tmp[AUX_GV];
     auto run = [&]() -> int {
-      const long long tsz = std::max<long long>({(long long)P * P * P, (long long)ai.N1[2] * ai.N1[1] * P,
-                                                  (long long)ai.N1[2] * P * P, (long long)P * P * nc[0],
-                                                  (long long)P * nc[1] * nc[0], (long long)nc[2] * nc[1] * p->vox[0],
-                                                  (long long)nc[2] * p->vox[1] * p->vox[0]});
-      HIP_TRY(hipMalloc(&t1, tsz * sizeof(double2)));
-      HIP_TRY(hipMalloc(&t2, tsz * sizeof(double2)));
-      HIP_TRY(hipMalloc(&ah, P3 * sizeof(double2)));
-      HIP_TRY(hipMalloc(&eh, P3 * sizeof(double2)));
-      HIP_TRY(hipMalloc(&Y, P3 * sizeof(double2)));
-      HIP_TRY(hipMalloc(&X, ncn * sizeof(double2)));
-      HIP_TRY(hipMalloc(&gv, std::max(nvox, ncn) * sizeof(double2)));
       HIP_TRY(hipMemsetAsync(Y, 0, P3 * sizeof(double2), st));
       HIP_TRY(launch_adjoint_weight(ai, lam + s0.out_off, st));
       for (int pp = 0; pp < 3; ++pp)
@@ -2028,18 +2104,11 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
       return GSM_OK;
     };
     rc = run();
-    hipFree(t1);
-    hipFree(t2);
-    hipFree(ah);
-    hipFree(eh);
-    hipFree(Y);
-    hipFree(X);
-    hipFree(gv);
-    if (rc) return cleanup(rc);
+    if (rc) return rc;
   }
   int worst = GSM_OK;
   fill_info(sys, exp, info, &worst);
-  return cleanup(worst);
+  return worst;
 }
 
 }  // extern "C"

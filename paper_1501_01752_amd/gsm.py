@@ -98,6 +98,7 @@ _SIGS = {
                                      C.POINTER(SolverOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(SolveInfo),
                                      C.c_void_p]),
+    "gsm_allocation_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gsm_profile_begin": (C.c_int, []),
     "gsm_profile_begin_only": (C.c_int, [C.c_char_p]),
     "gsm_profile_begin_sampled": (C.c_int, [C.c_char_p, C.c_int32]),
@@ -154,6 +155,14 @@ def profile_end():
     return {out[i].name.decode(): dict(launches=out[i].launches, ms=out[i].ms, bytes=out[i].bytes,
                                       flops=out[i].flops)
             for i in range(min(n.value, 64))}
+
+
+def allocation_stats():
+    """(allocations, bytes) the library has made since it was loaded (device
+    hipMalloc and pinned host hipHostMalloc)."""
+    n, b = C.c_int64(), C.c_int64()
+    _check(lib().gsm_allocation_stats(C.byref(n), C.byref(b)))
+    return n.value, b.value
 
 
 def default_opts(**kw):

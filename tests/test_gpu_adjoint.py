@@ -96,9 +96,15 @@ def test_autograd_function_gradcheck():
 
 
 def test_inverse_design_gradient_vs_finite_differences():
-    """32^3 voxel field in [1, 10], M = 12, three drives; adjoint gradient
-    against central differences (h = 1e-6) of FP64 forward solves on 8 seeded
-    voxels: |g_adj - g_fd| <= 1e-4 max|g| + 1e-10."""
+    """32^3 voxel field in [1, 10], M = 12, three drives: the adjoint gradient
+    of ||eps_eff - diag(4, 5, 6)||_F^2 (complex64 + FP64 refinement to 1e-9)
+    against central differences (h = 1e-6) on the 64 seeded voxels
+    rng(44).choice(32768, 64).  The difference solves run in FP64 to 1e-14
+    (warm-started from the base field), so their noise, about
+    1e-14 * |L| / h, stays far below the per-voxel gradients.  Per voxel:
+    |g_adj - g_fd| <= 1e-4 |g_fd| + 1e-6 max|g_fd|; the absolute floor is that
+    FD noise with room, and a relative error of 1e-4 is the finite-difference
+    truncation and the adjoint's mixed-precision solve error together."""
     gsm = G()
     M = (12, 12, 12)
     lam = 1 / 0.3
@@ -112,19 +118,56 @@ def test_inverse_design_gradient_vs_finite_differences():
     ee, E, info, st = plan.eff_tensor([inst], opts, save_fields=True)
     grad, _, _ = plan.eff_tensor_vjp([inst], E, ee, ee - TARGET[None], opts)
     grad = grad.cpu().numpy().ravel()
-    vox = np.random.default_rng(44).choice(eps.size, 8, replace=False)
+    vox = np.random.default_rng(44).choice(eps.size, 64, replace=False)
     fd_opts = gsm.default_opts(tol=1e-14, precision=gsm.GSM_FP64)
+    fd_opts.x0 = E.data_ptr()  # the base fields (three drives, the solve's layout)
     h = 1e-6
     fd = []
-    for v in vox:
+    for j, v in enumerate(vox):
         vals = []
-        for s in (+1, -1):
+        for sgn in (+1, -1):
             e2 = eps.copy().ravel()
-            e2[v] += s * h
+            e2[v] += sgn * h
             p2 = gsm.Plan(e2.reshape(eps.shape), (1, 1, 1), M)
-            ee2, _, _, _ = p2.eff_tensor([inst], fd_opts)
+            ee2, _, _, st2 = p2.eff_tensor([inst], fd_opts)
+            assert st2 == gsm.GSM_OK
             vals.append(float(np.sum(np.abs(ee2[0] - TARGET) ** 2)))
+            p2.close()
         fd.append((vals[0] - vals[1]) / (2 * h))
+        if j % 16 == 15:
+            say(f"finite differences: {j + 1} of 64 voxels")
     fd = np.array(fd)
-    say(f"grad {grad[vox]} fd {fd}")
-    assert np.abs(grad[vox] - fd).max() <= 1e-4 * np.abs(grad).max() + 1e-10
+    err = np.abs(grad[vox] - fd)
+    say(f"max |g_adj - g_fd| / |g_fd| = {np.max(err / np.abs(fd)):.3e}, max|g_fd| = {np.abs(fd).max():.3e}, "
+        f"max abs err = {err.max():.3e}")
+    assert np.all(err <= 1e-4 * np.abs(fd) + 1e-6 * np.abs(fd).max()), (grad[vox], fd)
+
+
+def test_repeated_calls_allocate_nothing():
+    """Once a plan has its contrast grids and the scheduler its pinned words
+    (the first calls), repeated gsm_solve, gsm_eff_tensor (fields kept by the
+    caller or left in the workspace) and gsm_eff_tensor_vjp calls make no
+    device or pinned-host allocation: every buffer they need is carved from
+    the caller's workspace.  The library counts its own allocations.  The
+    repeated gradients are bit-identical."""
+    gsm = G()
+    eps, k, lam = _grad_case(8, (2, 2, 2))
+    M = (2, 2, 2)
+    plan = gsm.Plan(eps, (1, 1, 1), M)
+    inst = gsm.make_instance(lam, k, M)
+    inst.eps_b = plan.basis_eps(inst)
+    opts = gsm.default_opts(tol=1e-11)
+    say("first eff tensor + vjp (plan state is built here)")
+    ee, E, _, _ = plan.eff_tensor([inst], opts, save_fields=True)
+    g0, _, _ = plan.eff_tensor_vjp([inst], E, ee, ee - TARGET[None], opts)
+    plan.solve([inst], opts)
+    g0 = g0.cpu().numpy()
+    n0 = gsm.allocation_stats()
+    for r in range(3):
+        say(f"repeated calls {r}")
+        ee2, _, _, st = plan.eff_tensor([inst], opts)
+        assert st == gsm.GSM_OK and np.array_equal(ee2, ee)
+        g, _, _ = plan.eff_tensor_vjp([inst], E, ee, ee - TARGET[None], opts)
+        assert np.array_equal(g.cpu().numpy(), g0)
+        plan.solve([inst], opts)
+    assert gsm.allocation_stats() == n0

@@ -332,3 +332,71 @@ def test_cfg2_stack_m15_vs_1d_reduction():
         off = Ed.copy()
         off[:, :, M[1], M[0]] = 0
         assert np.abs(off).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------- eff tensor at 31^3 harmonics ----
+
+def test_eff_tensor_cfg2_stack_m15():
+    """Layered stack (f = 0.4, eps 2.25 / 9) at M = 15 on the 64^3 grid,
+    complex64 Krylov + FP64 refinement, the three drives of gsm_eff_tensor:
+    every entry against the tensor D0 E0^-1 of the exact 1D reduction (the
+    (0, 0, mz) subspace is invariant for k || z), eps_zz against
+    1/[T^-1]_00 (the longitudinal drive sees -k0^2 T e_z = s_z delta_0),
+    eps_xx = eps_yy and vanishing off-diagonals."""
+    w = inputs.layered_stack_m15()
+    gsm = G()
+    lam, M = w["wavelength"], w["M"]
+    k = k_vector(lam, w["k_hat"])
+    plan = gsm.Plan(w["eps"], w["period"], M)
+    inst = gsm.make_instance(lam, k, M)
+    inst.eps_b = plan.basis_eps(inst)
+    say("eff tensor cfg2 stack M=15 mixed tol 1e-11")
+    ee, _, info, st = plan.eff_tensor([inst], gsm.default_opts(tol=1e-11))
+    assert st == gsm.GSM_OK and all(i["fft_size"] == 64 for i in info)
+    ee = ee[0]
+    Mz = M[2]
+    c1 = O.box_image(w["eps"], (0, 0, 2 * Mz))[:, 0, 0]
+    q0 = k / (2 * np.pi / lam)
+    fields = [O.solve_stack_1d(c1, Mz, q0, lam / w["period"][2], inst.eps_b, a) for a in np.eye(3)]
+    m = np.arange(-Mz, Mz + 1)
+    E0 = np.stack([f[:, Mz] for f in fields], axis=1)
+    D0 = np.stack([f @ c1[(0 - m) + 2 * Mz] for f in fields], axis=1)
+    ref = D0 @ np.linalg.inv(E0)
+    scale = np.abs(ref).max()
+    assert np.abs(ee - ref).max() <= 1e-9 * scale, (ee, ref)
+    T = c1[(m[:, None] - m[None, :]) + 2 * Mz]
+    assert abs(ee[2, 2] - 1.0 / np.linalg.inv(T)[Mz, Mz]) <= 1e-9 * scale
+    assert abs(ee[0, 0] - ee[1, 1]) <= 1e-9 * scale
+    off = ee - np.diag(np.diag(ee))
+    assert np.abs(off).max() <= 1e-12 * scale, off
+
+
+def test_eff_tensor_cfg2_sphere_m15_vs_fft_gmres_oracle():
+    """Sphere lattice (r = 0.3 Lambda, eps 4, 64^3 voxels) at M = 15, k || z:
+    gsm_eff_tensor (complex64 + FP64 refinement, three drives) against
+    D0 E0^-1 of the oracle's FFT + GMRES fields (residual 1e-12), and the
+    C4v symmetry of the cubic cell at k || z: eps_xx = eps_yy, zero
+    off-diagonals."""
+    w = inputs.sphere_lattice_m15()
+    gsm = G()
+    lam, M = w["wavelength"], w["M"]
+    k = k_vector(lam, w["k_hat"])
+    plan = gsm.Plan(w["eps"], w["period"], M)
+    inst = gsm.make_instance(lam, k, M)
+    inst.eps_b = plan.basis_eps(inst)
+    say("eff tensor cfg2 sphere M=15 mixed tol 1e-11")
+    ee, _, info, st = plan.eff_tensor([inst], gsm.default_opts(tol=1e-11))
+    assert st == gsm.GSM_OK
+    ee = ee[0]
+    c, q = oracle_case(w["eps"], w["period"], lam, k, M)
+    fields = []
+    for a in np.eye(3):
+        say(f"oracle FFT-GMRES field, drive {a}")
+        f, _ = O.solve_fft_gmres(c, M, q, inst.eps_b, a.astype(complex), (64, 64, 64), rtol=1e-12)
+        fields.append(f)
+    ref = O.eps_eff_from_fields(c, M, np.stack(fields))
+    scale = np.abs(ref).max()
+    assert np.abs(ee - ref).max() <= 1e-9 * scale, (ee, ref)
+    assert abs(ee[0, 0] - ee[1, 1]) <= 1e-9 * scale
+    off = ee - np.diag(np.diag(ee))
+    assert np.abs(off).max() <= 1e-9 * scale, off

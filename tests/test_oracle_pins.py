@@ -71,3 +71,29 @@ def test_maxwell_garnett_scalars_reproduce():
     for f, ref in ((0.155, 1.4213), (0.141, 1.4284)):
         e = em * (ei + 2 * em + 2 * f * (ei - em)) / (ei + 2 * em - f * (ei - em))
         assert abs(np.sqrt(e) - ref) < 1e-4
+
+
+def test_gradient_oracle_tensor_equals_schur_form():
+    """The gradient oracle's own fields, E0 and D0 (oracle/grad.py) give the
+    same eps_eff as the Schur-complement elimination of the harmonics m != 0
+    (an independent route, no D0 or E0 involved), on an asymmetric body at
+    oblique incidence where a wrong D0 index (c_m' instead of c_-m') or a
+    transposed E0 would change the result."""
+    import numpy as np
+    from oracle import grad as OG
+    from oracle import gsm as O
+    from paper_1501_01752_amd import inputs
+    eps = inputs.smooth_random_field(6, seed=4)
+    eps[1, 2, 3] = 9.5
+    M = (2, 1, 2)
+    lam = 1 / 0.3
+    period = (1.0, 1.1, 0.9)
+    k = np.array([0.3, 0.2, 0.93]) * 2 * np.pi / lam
+    c = O.box_image(eps, tuple(2 * m for m in M))
+    q = O.harmonic_q(k, lam, period, M)
+    ee = OG._fields_and_tensor(c, M, q, 4.5)[-1]
+    ref = O.eps_eff_schur(c, M, q)
+    assert np.abs(ee - ref).max() <= 1e-12 * np.abs(ref).max()
+    # the same tensor with another basis permittivity (eps_eff does not depend on it)
+    ee2 = OG._fields_and_tensor(c, M, q, 6.1)[-1]
+    assert np.abs(ee2 - ref).max() <= 1e-12 * np.abs(ref).max()
