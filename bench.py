@@ -22,8 +22,9 @@ extra step; the
 plain FP64 GPU solve of the same workload; the literal 4-solve case, the
 uneven 256-instance sweep, the 32^3-voxel inverse-design gradient and the
 M = 31 woodpile batch as further lines of the same JSON object; Table 1's
-single-solve workload at three sizes (context beside the paper's times); and
-the CPU oracle (FFT + SciPy GMRES, FP64) timed on a bounded sample.
+single-solve workload at three sizes (context beside the paper's times); the
+achievable copy bandwidth; and the CPU oracle (scipy.fft on the host threads
++ SciPy GMRES, FP64) timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -39,11 +40,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# published vector peaks: FP32 counts packed FMAs on every lane, FP64 FMAs
-ALU_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}
-# the same chip without packed FP32 (the kernels are built with it off):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+# vector peaks of the chip as these kernels are built (packed FP32 off):
+# 256 CUs x 64 lanes x 2 flop (one FMA per lane and clock) x 2.4 GHz, for
+# FP32 and FP64 alike; the published FP32 figure (157.3) counts packed FMAs
 ALU_UNPACKED_TFLOPS = {"c64": 78.6, "c128": 78.6}
+# the transforms are additions and multiplications that do not fuse into
+# FMAs: one flop per lane and clock, 256 x 64 x 2.4 GHz
+ALU_ADD_ISSUE_TFLOPS = 39.3
 TOL = 1e-9
 CPU_SAMPLE_S = 10.0
 
@@ -191,9 +194,15 @@ def uneven_sweep(gsm, inputs, steps, autotune):
             raise RuntimeError(f"sweep status {st}")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    # one more call with every launch timed: the batched product's HBM rate
+    gsm.profile_begin()
+    plan.solve(insts, opts)
+    prof = gsm.profile_end()
     return {"value": round(len(insts) / dt, 3), "unit": "solves/s", "instances": len(insts),
             "order_counts": [int(Ms.min()), int(Ms.max())], "ms_per_step": round(dt * 1e3, 3),
-            "max_rel_residual": max(i["rel_residual"] for i in info)}
+            "max_rel_residual": max(i["rel_residual"] for i in info),
+            "fft_sizes": sorted({int(i["fft_size"]) for i in info}),
+            "roofline": matvec_hbm(prof), "roofline_fp64_residual": matvec_hbm(prof, "c128")}
 
 
 def cpu_baseline(inputs):
@@ -222,10 +231,14 @@ def cpu_baseline(inputs):
     wall = time.perf_counter() - t0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {"value": n / wall, "unit": "solves/s", "cores": max(1, int(round(cpu / wall))),
+    host = host_cpu()
+    return {"value": n / wall, "unit": "solves/s", "cores": O.FFT_WORKERS,
+            "cpu_time_over_wall": round(cpu / wall, 2), "host": host,
+            "fft": f"scipy.fft, workers = {O.FFT_WORKERS} (OMP_NUM_THREADS, else the CPU affinity)",
             "kind": "oracle",
             "sample": f"{n} normal-incidence solves (sphere lattice and layered stack, M=15, x/y drives, "
-                      f"FP64 numpy FFT + scipy GMRES(30) to 1e-9), {its} iterations, {wall:.1f} s wall"}
+                      f"FP64 scipy.fft (all host threads) + scipy GMRES(30) to 1e-9), {its} iterations, "
+                      f"{wall:.1f} s wall"}
 
 
 def matvec_only(gsm, body, reps, systems=0):
@@ -267,26 +280,25 @@ def matvec_only(gsm, body, reps, systems=0):
 
 
 def roofline_of(name, v):
-    """Roofline entry of one kernel class.  The bound follows the algorithmic
-    intensity (flops per byte) against the ridge of the chip as this build
-    uses it (unpacked vector FMA rate over HBM bandwidth): vector ALU above
-    it, HBM below."""
+    """Roofline entry of one kernel class against the HBM bound: algorithmic
+    bytes of its launches over their summed durations, against the 8 TB/s
+    peak.  The vector-ALU side rides along: its algorithmic flops against the
+    unpacked FMA rate and against the issue rate of plain additions and
+    multiplications (what the transforms are made of)."""
     sec = v["ms"] * 1e-3
     gbs = v["bytes"] / sec / 1e9 if sec > 0 else 0.0
     tfs = v.get("flops", 0.0) / sec / 1e12 if sec > 0 else 0.0
     prec = "c128" if name.endswith("c128") else "c64"
-    ridge = ALU_UNPACKED_TFLOPS[prec] * 1e3 / HBM_PEAK_GBS
-    common = {"traffic": None, "kernel": name,
-              "avg_launch_us": round(v["ms"] * 1e3 / max(1, v["launches"]), 2), "timed_launches": v["launches"]}
-    if v["bytes"] > 0 and v.get("flops", 0.0) / v["bytes"] > ridge:
-        peak = ALU_PEAK_TFLOPS[prec]
-        return {"bound": "alu", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(tfs / peak, 4), **common,
-                "peak_unpacked": ALU_UNPACKED_TFLOPS[prec],
-                "frac_unpacked": round(tfs / ALU_UNPACKED_TFLOPS[prec], 4),
-                "hbm": {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}}
-    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), **common}
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+           "avg_launch_us": round(v["ms"] * 1e3 / max(1, v["launches"]), 2), "timed_launches": v["launches"]}
+    if v.get("flops", 0.0) > 0:
+        out["alu"] = {"achieved": round(tfs, 2), "unit": "TFLOP/s",
+                      "intensity_flop_per_byte": round(v["flops"] / max(v["bytes"], 1.0), 2),
+                      "peak_fma": ALU_UNPACKED_TFLOPS[prec], "frac_fma": round(tfs / ALU_UNPACKED_TFLOPS[prec], 4),
+                      "peak_add_issue": ALU_ADD_ISSUE_TFLOPS,
+                      "frac_add_issue": round(tfs / ALU_ADD_ISSUE_TFLOPS, 4)}
+    return out
 
 
 def counted_traffic(name, systems=64):
@@ -375,8 +387,13 @@ def woodpile(gsm, inputs, steps):
         worst = max(worst, max(i["rel_residual"] for i in info))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    gsm.profile_begin()
+    plan.solve(insts, opts)
+    prof = gsm.profile_end()
     return {"value": round(16 * steps / dt, 3), "unit": "solves/s", "solves_per_step": 16,
-            "ms_per_step": round(dt / steps * 1e3, 1), "max_rel_residual": worst}
+            "ms_per_step": round(dt / steps * 1e3, 1), "max_rel_residual": worst,
+            "roofline": matvec_hbm(prof), "roofline_fp64_residual": matvec_hbm(prof, "c128"),
+            "kernels": kernel_table(prof)}
 
 
 # Table 1 of the paper: GPU seconds per solve at 16^3, 32^3 and 64^3 harmonics
@@ -422,19 +439,61 @@ def table1(gsm, inputs, reps):
             "note": "paper_gpu_ms: the paper's Table 1 (FP64, its 2013 GPU, 16/32/64 harmonics per axis), context"}
 
 
-def matvec_hbm(prof):
-    """The complex64 matrix-vector product as a whole (passes A, B and C of
-    the profiled step): algorithmic bytes over the summed launch durations,
-    against the HBM peak."""
-    parts = [prof.get(f"pass_{x}_c64") for x in "abc"]
+def matvec_hbm(prof, prec="c64"):
+    """The matrix-vector product as a whole (passes A, B and C of a profiled
+    step): algorithmic bytes over the summed launch durations, against the
+    HBM peak; the bytes both on the grids in use and on the smallest
+    admissible grids (P_min >= 4M + 1, no prime factor above 5: the bytes
+    model's, so that a grid larger than needed does not count as work)."""
+    parts = [prof.get(f"pass_{x}_{prec}") for x in "abc"]
     if not all(parts):
         return None
     ms = sum(v["ms"] for v in parts)
     gbs = sum(v["bytes"] for v in parts) / (ms * 1e-3) / 1e9
-    return {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "launches": parts[0]["launches"], "ms": round(ms, 3),
-            "note": "passes A+B+C in complex64 over the extra step that times every class; pass B is "
-                    "vector-ALU bound, so the product stays below the HBM roofline"}
+    gbs_min = sum(v["bytes_min"] for v in parts) / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs_min, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs_min / HBM_PEAK_GBS, 4), "bytes": "B_mv on P_min",
+            "achieved_grid_in_use": round(gbs, 1), "frac_grid_in_use": round(gbs / HBM_PEAK_GBS, 4),
+            "launches": parts[0]["launches"], "ms": round(ms, 3), "precision": prec,
+            "per_pass_GBps": {f"pass_{x}": round(v["bytes_min"] / (v["ms"] * 1e-3) / 1e9, 1)
+                              for x, v in zip("abc", parts)}}
+
+
+def host_cpu():
+    """CPU model and thread count of the host (for the CPU baseline)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def copy_bandwidth():
+    """Achievable HBM rate of a plain shader copy: torch's elementwise negation
+    of 2^28 float32 values (read 1 GiB, write 1 GiB), best of five."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.neg(src, out=dst)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    gbs = 2 * (1 << 30) / (best * 1e-3) / 1e9
+    return {"GBps": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes": 2 * (1 << 30),
+            "kernel": "torch.neg, 1 GiB in + 1 GiB out, best of 5"}
 
 
 def main():
@@ -573,6 +632,7 @@ def main():
     wood = woodpile(gsm, inputs, args.woodpile_steps) if args.woodpile_steps > 0 else None
     tab1 = table1(gsm, inputs, args.table1_reps) if args.table1_reps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
+    copy_bw = copy_bandwidth()
     per_step = total // args.steps
     line = {
         "metric": "GSM solves/sec to 1e-9 rel. residual at 31^3 orders; matvec HBM GB/s vs peak",
@@ -593,6 +653,7 @@ def main():
         "roofline": roofline,
         "roofline_one_group": one_group,
         "matvec_hbm": matvec,
+        "copy_bandwidth": copy_bw,
         "fp64_gpu_solve": fp64,
         "as_configured": as_configured,
         "uneven_sweep": sweep,

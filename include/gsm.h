@@ -310,6 +310,10 @@ typedef struct gsm_kernel_stat {
   double ms;
   double bytes;
   double flops;     /* algorithmic real floating-point operations (FFT passes) */
+  double bytes_min; /* algorithmic bytes with each launch's grid replaced by the
+                       smallest admissible one, P >= 4 max M + 1 with no prime
+                       factor above 5 (the bytes model's grid; equal to `bytes`
+                       outside the FFT passes) */
 } gsm_kernel_stat;
 
 /* Start collecting (clears earlier records).  Calls on different plans may

@@ -20,9 +20,26 @@ Conventions (stated here so that a reader can check them against the paper):
   index n + N_a; c_n = (1/|cell|) * integral over the cell of
   eps(r) exp(-i G_n . r).
 """
+import os
+
 import numpy as np
+import scipy.fft
 import scipy.linalg
 import scipy.sparse.linalg
+
+# FFTs of the FFT route run on the host threads this process may use (the
+# same DFT as numpy's; only the rounding order can differ): OMP_NUM_THREADS
+# when set, else the CPU affinity
+def _fft_workers():
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    if hasattr(os, "sched_getaffinity"):
+        return max(1, len(os.sched_getaffinity(0)))
+    return os.cpu_count() or 1
+
+
+FFT_WORKERS = _fft_workers()
 
 
 # ---------------------------------------------------------------- geometry --
@@ -197,14 +214,14 @@ def contrast_convolution_fft(c, M, eps_b, x, P):
             nx = np.arange(-2 * M[0], 2 * M[0] + 1)
             grid[nz % Pz, ny % Py, nx % Px] = c[nz + nz0, ny + ny0, nx + nx0] / eps_b
     grid[0, 0, 0] -= 1.0
-    g = np.fft.ifftn(grid) * (Px * Py * Pz)
+    g = scipy.fft.ifftn(grid, workers=FFT_WORKERS) * (Px * Py * Pz)
     mz = np.arange(-M[2], M[2] + 1) % Pz
     my = np.arange(-M[1], M[1] + 1) % Py
     mx = np.arange(-M[0], M[0] + 1) % Px
     X = np.zeros((3, Pz, Py, Px), dtype=np.complex128)
     X[:, mz[:, None, None], my[None, :, None], mx[None, None, :]] = x
-    xr = np.fft.ifftn(X, axes=(1, 2, 3)) * (Px * Py * Pz)
-    W = np.fft.fftn(xr * g[None], axes=(1, 2, 3)) / (Px * Py * Pz)
+    xr = scipy.fft.ifftn(X, axes=(1, 2, 3), workers=FFT_WORKERS) * (Px * Py * Pz)
+    W = scipy.fft.fftn(xr * g[None], axes=(1, 2, 3), workers=FFT_WORKERS) / (Px * Py * Pz)
     return W[:, mz[:, None, None], my[None, :, None], mx[None, None, :]]
 
 

@@ -725,6 +725,7 @@ struct ProfRec {
   int group;
   double flops;   // resolved algorithmic floating-point operations
   double funit;   // operations per working system (step records)
+  double pmin_ratio;  // bytes on the smallest admissible grid over bytes on the grid used
 };
 
 // Shared by every host thread that calls the library (calls on different
@@ -759,7 +760,7 @@ hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStre
                  double flops = 0.0, double funit = 0.0) {
   if (t_capturing || !g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f();
   if (g_prof.every > 1 && g_prof.seq[cls].fetch_add(1) % g_prof.every != 0) return f();
-  ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit};
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit, 1.0};
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     r.a = prof_event();
@@ -779,10 +780,10 @@ hipError_t timed(int cls, bool dbl, double bytes, int step, double unit, hipStre
 // kernels: extended launches stamped by the dispatch packet).
 template <class F>
 hipError_t timed_ext(int cls, bool dbl, double bytes, int step, double unit, hipStream_t st, F&& f, double flops,
-                     double funit) {
+                     double funit, double pmin_ratio) {
   if (t_capturing || !g_prof.on || (g_prof.only >= 0 && g_prof.only != cls)) return f(nullptr, nullptr);
   if (g_prof.every > 1 && g_prof.seq[cls].fetch_add(1) % g_prof.every != 0) return f(nullptr, nullptr);
-  ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit};
+  ProfRec r{cls * 2 + (dbl ? 1 : 0), nullptr, nullptr, bytes, step, unit, t_group_tag, flops, funit, pmin_ratio};
   {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     r.a = prof_event();
@@ -824,10 +825,24 @@ void prof_resolve(const int* jdone, int S, long long n, size_t vb) {
 struct PassBytes {
   double a, b, c;
 };
-PassBytes pass_bytes(const GroupShape& g, size_t bc) {
-  const double vec = (double)g.n * bc, mid = 3.0 * g.npencil * g.P * bc;  // padding not counted
-  const double grid = (double)g.P * g.P * g.P * (bc / 2);
+PassBytes pass_bytes(const GroupShape& g, size_t bc, int P = 0) {
+  if (P <= 0) P = g.P;
+  const double vec = (double)g.n * bc, mid = 3.0 * g.npencil * P * bc;  // padding not counted
+  const double grid = (double)P * P * P * (bc / 2);
   return {vec + mid, 2 * mid + grid, mid + 2 * vec};
+}
+
+// The smallest grid the exact product admits, P >= 4 max_a M_a + 1, among
+// sizes with no prime factor above 5: the grid of the bytes model, so that a
+// larger grid in use does not inflate the algorithmic bytes.
+int pmin_smooth(const int M[3]) {
+  int p = 4 * std::max(M[0], std::max(M[1], M[2])) + 1;
+  for (;; ++p) {
+    int r = p;
+    for (int f : {2, 3, 5})
+      while (r % f == 0) r /= f;
+    if (r == 1) return p;
+  }
 }
 
 // Algorithmic floating-point operations of the three passes per system: the
@@ -860,6 +875,14 @@ int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step
   // the contrast grid is shared by the systems of a launch: counted once
   const double grid = (double)a.g.P * a.g.P * a.g.P * sizeof(T);
   const double nb_b = step >= 0 ? 0.0 : nwork * (pb.b - grid) + grid;
+  // the same bytes on the smallest admissible grid, as ratios per class
+  const int pm = pmin_smooth(a.g.M);
+  PassBytes pbm = pass_bytes(a.g, sizeof(cplx<T>), pm);
+  if (a.mode == PC_GREEN || a.mode == PC_CONV) pbm.c -= vec;
+  if (a.mode == PC_ADJ_RESID) pbm.c += vec;
+  const double gridm = (double)pm * pm * pm * sizeof(T);
+  const double nsys_b = step >= 0 ? (double)std::max(1, a.g.S) : (double)std::max(1, nwork);
+  const double rb = (nsys_b * (pbm.b - gridm) + gridm) / (nsys_b * (pb.b - grid) + grid);
   auto with_ev = [](PassArgs<T> q, hipEvent_t e0, hipEvent_t e1) {
     q.ev0 = e0;
     q.ev1 = e1;
@@ -867,13 +890,13 @@ int apply_passes(PassArgs<T> a, int pa_mode, hipStream_t st, int nwork, int step
   };
   HIP_TRY(timed_ext(K_PASS_A, dbl, step >= 0 ? 0.0 : nwork * pb.a, step, pb.a, st,
                     [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_a<T>(with_ev(aa, e0, e1), st); },
-                    nf * pf.a, pf.a));
+                    nf * pf.a, pf.a, pbm.a / pb.a));
   HIP_TRY(timed_ext(K_PASS_B, dbl, nb_b, step, pb.b - grid + grid / std::max(1, a.g.S), st,
                     [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_b<T>(with_ev(a, e0, e1), st); },
-                    nf * pf.b, pf.b));
+                    nf * pf.b, pf.b, rb));
   HIP_TRY(timed_ext(K_PASS_C, dbl, step >= 0 ? 0.0 : nwork * pb.c, step, pb.c, st,
                     [&](hipEvent_t e0, hipEvent_t e1) { return launch_pass_c<T>(with_ev(a, e0, e1), st); },
-                    nf * pf.c, pf.c));
+                    nf * pf.c, pf.c, pbm.c / pb.c));
   return GSM_OK;
 }
 
@@ -1939,6 +1962,7 @@ int gsm_profile_end(gsm_kernel_stat* out, int32_t max, int32_t* n_out) {
     st[r.cls].launches += 1;
     st[r.cls].ms += ms;
     st[r.cls].bytes += r.step == -1 ? r.bytes : 0.0;
+    st[r.cls].bytes_min += r.step == -1 ? r.bytes * r.pmin_ratio : 0.0;
     st[r.cls].flops += r.step == -1 ? r.flops : 0.0;
   }
   g_prof.recs.clear();

@@ -55,7 +55,7 @@ class SolveInfo(C.Structure):
 
 class KernelStat(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("ms", C.c_double),
-                ("bytes", C.c_double), ("flops", C.c_double)]
+                ("bytes", C.c_double), ("flops", C.c_double), ("bytes_min", C.c_double)]
 
 
 class GsmError(RuntimeError):
@@ -148,12 +148,12 @@ def profile_begin(only=None, every=1):
 
 
 def profile_end():
-    """Per-kernel-class {launches, ms, bytes} since profile_begin()."""
+    """Per-kernel-class {launches, ms, bytes, flops, bytes_min} since profile_begin()."""
     out = (KernelStat * 64)()
     n = C.c_int32()
     _check(lib().gsm_profile_end(out, 64, C.byref(n)))
     return {out[i].name.decode(): dict(launches=out[i].launches, ms=out[i].ms, bytes=out[i].bytes,
-                                      flops=out[i].flops)
+                                      flops=out[i].flops, bytes_min=out[i].bytes_min)
             for i in range(min(n.value, 64))}
 
 
