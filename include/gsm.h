@@ -92,8 +92,22 @@ enum {
  * are identical to those of separate launches.  BiCGStab steps are always
  * separate launches.  Off by default: on the MI355X with ROCm 7.2 the graph
  * launches ran 3-9 % slower than separate launches for these kernels. */
-/* gsm_apply modes */
-enum { GSM_APPLY_FORWARD = 0, GSM_APPLY_ADJOINT = 1 };
+/* gsm_apply modes: the E-field operator of Eq.(4) or its adjoint, or the
+ * H-field operator of Eq.(5) */
+enum { GSM_APPLY_FORWARD = 0, GSM_APPLY_ADJOINT = 1, GSM_APPLY_FORWARD_H = 2 };
+/* gsm_solver_opts.formulation.  GSM_FORM_E: the electric-field system,
+ * Eq.(4).  GSM_FORM_H: the magnetic-field system of Eq.(5),
+ *   H_m = H^inc_m + q_m x w_m / (eps_b - |q_m|^2),
+ *   w_m = sum_m' [delta_mm' - eps_b eta_{m-m'}] (q_m' x H_m'),
+ * q_m = k_m / k0, eta_n the Fourier image of 1/eps (the paper's (eps_b/eps)
+ * Toeplitz matrix, taken from the exact image of 1/eps, not by inverting
+ * that of eps: "Calculation details"), H^inc_m = delta_m0 a.  Same passes:
+ * the curl q x is applied per harmonic before the contrast product, the
+ * plane pass multiplies by 1 - eps_b eta(r), and the last pass applies
+ * q x / (eps_b - |q|^2).  The H system is solved (gsm_solve) and searched
+ * for poles (gsm_pole_search); the effective tensor, the adjoint and the
+ * gradient are defined on the E system only (GSM_E_ARG otherwise). */
+enum { GSM_FORM_E = 0, GSM_FORM_H = 1 };
 
 typedef struct gsm_plan_s* gsm_plan_t;
 
@@ -151,7 +165,7 @@ typedef struct gsm_solver_opts {
                          one group's Krylov cycles, when few of its systems still
                          work, overlap with another group's launches.  The
                          workspace query must be given the same value. */
-  int32_t reserved;   /* set to 0 */
+  int32_t formulation; /* GSM_FORM_E (default) or GSM_FORM_H */
 } gsm_solver_opts;
 
 /* Result of one system (instance, drive). */
@@ -204,9 +218,74 @@ int gsm_basis_eps(gsm_plan_t plan, const gsm_instance* inst, double* eps_b);
 int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out);
 int gsm_plan_destroy(gsm_plan_t plan);
 
+/* Analytic bodies.  The paper builds its Toeplitz matrices from exact
+ * Fourier images of simple shapes, spheres and polyhedra combined into a
+ * structure ("Calculation details"), rather than from mesh samples.  A
+ * shape body is a host permittivity eps_host holding inclusions that overlap
+ * neither each other nor their own periodic copies (the caller's
+ * responsibility; each inclusion's extent must not exceed the period on any
+ * axis, else GSM_E_ARG).  Its coefficients are
+ *   c_n = eps_host delta_n0 + sum_i (eps_i - eps_host) S_i(G_n),
+ *   S_i(G) = (1/|cell|) integral over inclusion i of exp(-i G.r) dr,
+ * G_n = 2 pi (n_x/Lambda_x, n_y/Lambda_y, n_z/Lambda_z), evaluated in FP64
+ * on the device: for a sphere of radius R, or an axis-aligned ellipsoid
+ * with semi-axes (a, b, c), (volume/|cell|) 3 (sin u - u cos u)/u^3
+ * exp(-i G.r0) with u = |(a G_x, b G_y, c G_z)|; for an axis-aligned box with
+ * half-sides (a, b, c), (8abc/|cell|) sinc(a G_x) sinc(b G_y) sinc(c G_z)
+ * exp(-i G.r0), sinc(x) = sin(x)/x. */
+enum { GSM_SHAPE_SPHERE = 0, GSM_SHAPE_ELLIPSOID = 1, GSM_SHAPE_BOX = 2 };
+typedef struct gsm_shape {
+  int32_t kind;     /* GSM_SHAPE_* */
+  int32_t reserved; /* must be 0 */
+  double centre[3]; /* r0, in the period's length unit */
+  double size[3];   /* sphere: radius in size[0] (others ignored); ellipsoid:
+                       semi-axes; box: half-sides; all > 0 */
+  double eps;       /* permittivity inside, > 0 */
+} gsm_shape;
+
+typedef struct gsm_shape_body {
+  double period[3];
+  double eps_host;          /* > 0 */
+  int32_t n_shapes;         /* >= 0 */
+  int32_t reserved;         /* must be 0 */
+  const gsm_shape* shapes;  /* host, n_shapes entries; copied */
+} gsm_shape_body;
+
+/* Plan of an analytic shape body: as gsm_plan, with the coefficients above
+ * in place of the voxel image.  The basis-permittivity policy uses the mean
+ * c_0 and the range of eps_host and the inclusions' values.  Gradients with
+ * respect to voxels (gsm_eff_tensor_vjp) are refused on such a plan. */
+int gsm_plan_shapes(const gsm_shape_body* body, const gsm_plan_opts* opts, gsm_plan_t* out);
+
+/* Coefficients given directly (an image computed elsewhere). */
+typedef struct gsm_coeff_body {
+  double period[3];
+  int32_t n_max[3];     /* the array covers |n_a| <= n_max[a]; needs n_max[a] >= 2 m_max[a] */
+  int32_t reserved;     /* must be 0 */
+  const double* coef;   /* host complex128 (re, im) [2 n_max z + 1][2 n_max y + 1][2 n_max x + 1],
+                           index n_a + n_max[a]; the Fourier image of a real permittivity
+                           (c_-n = conj(c_n) to 1e-12 of the largest entry, c_0 > 0), else
+                           GSM_E_ARG; copied */
+  double eps_min;       /* range of the permittivity, 0 < eps_min <= eps_max: the basis- */
+  double eps_max;       /* permittivity policy scans [0.5 eps_min, 2 eps_max] */
+  const double* coef_inv; /* NULL, or the image of 1/eps in the layout of coef (needed by the
+                             H-field system); copied */
+} gsm_coeff_body;
+
+/* Plan from given coefficients: the |n_a| <= 2 m_max[a] block is taken.  As
+ * gsm_plan_shapes otherwise (no voxel gradient). */
+int gsm_plan_from_coeffs(const gsm_coeff_body* body, const gsm_plan_opts* opts, gsm_plan_t* out);
+
 /* Copy the plan's coefficients c_n to host memory: (4 m_max[2]+1) x
  * (4 m_max[1]+1) x (4 m_max[0]+1) complex128, [nz][ny][nx], index n_a + 2 m_max[a]. */
 int gsm_plan_coefficients(gsm_plan_t plan, double* c_out);
+
+/* Copy the plan's coefficients of 1/eps (the H-field system's), layout of
+ * gsm_plan_coefficients.  GSM_E_ARG if the plan holds none (a coefficient
+ * plan made without coef_inv).  Voxel plans take the exact image of the
+ * piecewise-constant 1/eps, shape plans the analytic images with the
+ * weights 1/eps_i - 1/eps_host. */
+int gsm_plan_inverse_coefficients(gsm_plan_t plan, double* c_out);
 
 /* Copy the band-limited permittivity grid used for order counts M and grid
  * P: eps_M(r_j) = sum_{|n_a| <= 2 M_a} c_n exp(2 pi i n.j / P), real,
@@ -242,7 +321,8 @@ int gsm_solve(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
               gsm_solve_info* info, void* stream);
 
 /* Apply the operator of Eq.(4) once: y = A x (GSM_APPLY_FORWARD) or
- * y = A^H x (GSM_APPLY_ADJOINT), for every (instance, drive) vector, in
+ * y = A^H x (GSM_APPLY_ADJOINT), or that of Eq.(5) (GSM_APPLY_FORWARD_H, see
+ * GSM_FORM_H), for every (instance, drive) vector, in
  * complex128 (precision GSM_FP64) or complex64 (GSM_MIXED: x and y are then
  * interleaved float pairs).  Device pointers.  For parity tests and timing. */
 int gsm_apply(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst, int32_t precision,
@@ -278,6 +358,76 @@ int gsm_eff_tensor_vjp(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst
                        const gsm_solver_opts* opts, const double* E_save,
                        const double* eps_eff, const double* gbar, double* grad_vox, void* ws,
                        size_t ws_bytes, gsm_solve_info* info, void* stream);
+
+/* ---------------------------------------------------------- pole search */
+
+/* Mode propagation constants by the pole search of the paper's section on
+ * mode propagation, Eqs.(6)-(10).  For one direction k_hat and drive a, the
+ * zeroth-order field component xi(kappa) = E_{component, m = 0} of the solve
+ * with k_inc = kappa k_hat (all else fixed) is meromorphic in kappa; its
+ * poles eta_j are the modes' propagation constants, n_eff = eta / k0.
+ * - The mesh: N_d + N_p equidistant kappa over [kappa_min, kappa_max] (one
+ *   batched solve of all of them).  Eq.(9) takes one equation from each of
+ *   the N_p windows of N_d + 1 consecutive mesh points, with xi_i
+ *   multiplying the divided-difference weights 1/prod_{j != i}(kappa_i -
+ *   kappa_j) (the printed equation shows it in a denominator); the monic
+ *   polynomial's zeros (Eq.(7)) are the eigenvalues of its companion matrix;
+ *   the amplitudes zeta_j follow from Eq.(10) with the middle window's nodes.
+ * - The basis permittivity is one value for the whole mesh (xi must be one
+ *   function of kappa): the query's eps_b if > 0 (GSM_E_SINGULAR if some mesh
+ *   point violates the 1e-3 margin), else the plan's mean permittivity if it
+ *   keeps the margin at every mesh point, else the value of [0.5 eps_min,
+ *   2 eps_max] with the largest smallest margin over the mesh.
+ * - The fit (Eq.(9) by Gaussian elimination, the companion matrix by shifted
+ *   QR, Eq.(10)) runs in FP64 in a HIP kernel, one thread per query. */
+#define GSM_POLE_MAX_NP 8
+#define GSM_POLE_MAX_ND 32
+
+typedef struct gsm_pole_query {
+  double wavelength;
+  double k_hat[3];    /* direction of k_inc (normalised by the library; nonzero) */
+  int32_t M[3];       /* order counts */
+  int32_t n_poles;    /* N_p, 1 .. GSM_POLE_MAX_NP (the paper suggests about 5) */
+  int32_t n_div;      /* N_d, N_p < N_d <= GSM_POLE_MAX_ND (the paper suggests about 10) */
+  int32_t component;  /* 0, 1, 2: the x, y or z component of the zeroth order */
+  double pol[6];      /* drive a (re, im of x, y, z) */
+  double kappa_min;   /* mesh interval of |k_inc|, absolute (1/length), 0 < min < max */
+  double kappa_max;
+  double eps_b;       /* <= 0: the policy above */
+} gsm_pole_query;
+
+typedef struct gsm_pole_result {
+  int32_t status;            /* worst status of the mesh solves; GSM_E_SINGULAR if Eq.(9)
+                                or the eigenvalue iteration failed */
+  int32_t n_poles;
+  int32_t best;              /* index of the pole with real part in [kappa_min, kappa_max]
+                                and the largest |zeta|; -1 if none */
+  int32_t iterations;        /* Krylov iterations summed over the mesh */
+  double eta[GSM_POLE_MAX_NP][2];   /* poles (re, im), ascending real part */
+  double zeta[GSM_POLE_MAX_NP][2];  /* amplitudes */
+  double n_eff;              /* Re eta[best] / k0, 0 if best < 0 */
+  double eps_b;              /* the basis permittivity of the mesh */
+  double max_rel_residual;   /* over the mesh solves */
+} gsm_pole_result;
+
+/* Workspace bytes of gsm_pole_search for these queries and options. */
+int gsm_pole_workspace_size(gsm_plan_t plan, int32_t n_q, const gsm_pole_query* q,
+                            const gsm_solver_opts* opts, size_t* bytes);
+
+/* Run the mesh solves of every query in one batched call (queries of equal
+ * orders share launches) and fit the poles.  out: host, n_q results.
+ * Returns the worst status.  Synchronises `stream`. */
+int gsm_pole_search(gsm_plan_t plan, int32_t n_q, const gsm_pole_query* q,
+                    const gsm_solver_opts* opts, void* ws, size_t ws_bytes, gsm_pole_result* out,
+                    void* stream);
+
+/* The fit alone, on samples already on the device: n problems of N_d + N_p
+ * points each; kappa [n][N_d + N_p] doubles, xi [n][N_d + N_p] complex128;
+ * eta and zeta [n][N_p] complex128 out; status [n] int32 out (GSM_OK or
+ * GSM_E_SINGULAR; eta, zeta zero then).  Device pointers, stream-ordered
+ * (no synchronisation). */
+int gsm_pole_fit(int32_t n, int32_t n_poles, int32_t n_div, const double* kappa, const double* xi,
+                 double* eta, double* zeta, int32_t* status, void* stream);
 
 /* Launch graphs of a plan so far: *captured = graphs captured and
  * instantiated, *launched = graph launches (each runs a few Krylov steps of

@@ -128,12 +128,16 @@ constexpr size_t kGraphsPerSlot = 32;
 struct gsm_plan_s {
   int device = 0;
   double period[3]{};
-  int vox[3]{};
+  int vox[3]{1, 1, 1};
+  bool voxel_body = false;  // coefficients from voxels (gradients with respect to them are defined)
   int mmax[3]{};
   int nc[3]{};  // 4 m_max + 1
   double eps_mean = 0, eps_min = 0, eps_max = 0;
   double2* d_coef = nullptr;
-  std::map<std::array<int, 4>, Grid> grids;
+  double2* d_coef_inv = nullptr;  // image of 1/eps (the H-field system); null if not given
+  // real-space grids per (M, P, kind): kind 0 the permittivity (Eq.(4)),
+  // kind 1 its inverse (Eq.(5))
+  std::map<std::array<int, 5>, Grid> grids;
   RunSlot slots[kSlots];
   bool autotune = false;
   std::string tune_cache;  // file of tuning results ("" = none)
@@ -180,6 +184,77 @@ int check_plan_opts(const gsm_plan_opts* o) {
   return GSM_OK;
 }
 
+int check_shape_body(const gsm_shape_body* b) {
+  if (!b) return fail(GSM_E_ARG, "shape body is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(b->period[a])) return fail(GSM_E_NONFINITE, "period[%d] is not finite", a);
+    if (!(b->period[a] > 0)) return fail(GSM_E_ARG, "period[%d] must be > 0", a);
+  }
+  if (!std::isfinite(b->eps_host)) return fail(GSM_E_NONFINITE, "eps_host is not finite");
+  if (!(b->eps_host > 0)) return fail(GSM_E_ARG, "eps_host must be > 0");
+  if (b->n_shapes < 0 || (b->n_shapes > 0 && !b->shapes)) return fail(GSM_E_ARG, "bad shape list");
+  if (b->reserved != 0) return fail(GSM_E_ARG, "reserved shape-body field must be 0");
+  for (int k = 0; k < b->n_shapes; ++k) {
+    const gsm_shape& sh = b->shapes[k];
+    if (sh.kind != GSM_SHAPE_SPHERE && sh.kind != GSM_SHAPE_ELLIPSOID && sh.kind != GSM_SHAPE_BOX)
+      return fail(GSM_E_ARG, "shape %d: unknown kind %d", k, sh.kind);
+    if (sh.reserved != 0) return fail(GSM_E_ARG, "shape %d: reserved field must be 0", k);
+    if (!std::isfinite(sh.eps)) return fail(GSM_E_NONFINITE, "shape %d: eps is not finite", k);
+    if (!(sh.eps > 0)) return fail(GSM_E_ARG, "shape %d: eps must be > 0", k);
+    const int nsz = sh.kind == GSM_SHAPE_SPHERE ? 1 : 3;
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(sh.centre[a])) return fail(GSM_E_NONFINITE, "shape %d: centre is not finite", k);
+      const double sz = sh.size[a < nsz ? a : 0];
+      if (!std::isfinite(sz)) return fail(GSM_E_NONFINITE, "shape %d: size is not finite", k);
+      if (!(sz > 0)) return fail(GSM_E_ARG, "shape %d: size must be > 0", k);
+      // the image formula needs the body apart from its own periodic copies
+      if (2.0 * sz > b->period[a])
+        return fail(GSM_E_ARG, "shape %d: extent %g along axis %d exceeds the period %g", k, 2.0 * sz, a,
+                    b->period[a]);
+    }
+  }
+  return GSM_OK;
+}
+
+int check_coeff_body(const gsm_coeff_body* b, const gsm_plan_opts* o) {
+  if (!b) return fail(GSM_E_ARG, "coefficient body is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(b->period[a])) return fail(GSM_E_NONFINITE, "period[%d] is not finite", a);
+    if (!(b->period[a] > 0)) return fail(GSM_E_ARG, "period[%d] must be > 0", a);
+    if (b->n_max[a] < 2 * o->m_max[a])
+      return fail(GSM_E_ARG, "n_max[%d]=%d < 2 m_max[%d]=%d: the Toeplitz matrix needs |n| <= 2 M", a, b->n_max[a], a,
+                  2 * o->m_max[a]);
+  }
+  if (b->reserved != 0) return fail(GSM_E_ARG, "reserved coefficient-body field must be 0");
+  if (!b->coef) return fail(GSM_E_ARG, "coefficients are NULL");
+  if (!(std::isfinite(b->eps_min) && std::isfinite(b->eps_max)))
+    return fail(GSM_E_NONFINITE, "eps_min / eps_max not finite");
+  if (!(b->eps_min > 0 && b->eps_max >= b->eps_min)) return fail(GSM_E_ARG, "need 0 < eps_min <= eps_max");
+  const long long sx = 2LL * b->n_max[0] + 1, sy = 2LL * b->n_max[1] + 1, sz = 2LL * b->n_max[2] + 1;
+  const long long n = sx * sy * sz;
+  const long long i0 = (long long)(b->n_max[2] * sy + b->n_max[1]) * sx + b->n_max[0];
+  // the image of a real function: c_{-n} = conj(c_n) (the real-space grid
+  // keeps only the real part), c_0 real and positive
+  auto check = [&](const double* c, const char* what) -> int {
+    double big = 0;
+    for (long long i = 0; i < 2 * n; ++i) {
+      if (!std::isfinite(c[i])) return fail(GSM_E_NONFINITE, "%s: coefficient %lld is not finite", what, i / 2);
+      big = std::max(big, std::fabs(c[i]));
+    }
+    for (long long i = 0; i < n; ++i) {
+      const long long j = n - 1 - i;  // index of -n
+      if (std::fabs(c[2 * i] - c[2 * j]) > 1e-12 * big || std::fabs(c[2 * i + 1] + c[2 * j + 1]) > 1e-12 * big)
+        return fail(GSM_E_ARG, "%s are not those of a real function (c_-n != conj(c_n) at entry %lld)", what, i);
+    }
+    if (!(c[2 * i0] > 0)) return fail(GSM_E_ARG, "%s: c_0 (the mean) must be > 0", what);
+    return GSM_OK;
+  };
+  int rc;
+  if ((rc = check(b->coef, "coefficients"))) return rc;
+  if (b->coef_inv && (rc = check(b->coef_inv, "inverse-permittivity coefficients"))) return rc;
+  return GSM_OK;
+}
+
 int check_instance(const gsm_instance& in, const int* mmax, int i, bool need_drives) {
   if (!std::isfinite(in.wavelength)) return fail(GSM_E_NONFINITE, "instance %d: wavelength not finite", i);
   if (!(in.wavelength > 0)) return fail(GSM_E_ARG, "instance %d: wavelength must be > 0", i);
@@ -216,7 +291,8 @@ int check_solver_opts(const gsm_solver_opts* s) {
     return fail(GSM_E_ARG, "BiCGStab keeps six vectors per system: restart must be >= 5");
   if (s->flags & ~(GSM_OUT_HOST | GSM_SOLVE_GRAPH)) return fail(GSM_E_ARG, "unknown solver flags");
   if (s->group_max < 0) return fail(GSM_E_ARG, "group_max must be >= 0");
-  if (s->reserved != 0) return fail(GSM_E_ARG, "reserved solver field must be 0");
+  if (s->formulation != GSM_FORM_E && s->formulation != GSM_FORM_H)
+    return fail(GSM_E_ARG, "unknown formulation %d", s->formulation);
   return GSM_OK;
 }
 
@@ -326,6 +402,7 @@ int resolve_eps_b(const double* period, double eps_mean, double eps_min, double 
 
 struct SysDesc {
   int inst, drive;
+  int form;  // FORM_E or FORM_H
   int M[3];
   int P;
   long long n;        // complex values
@@ -403,6 +480,9 @@ int build_systems(gsm_plan_s* plan, int n_inst, const gsm_instance* inst, const 
       }
       s.par.eps_b = eb;
       s.par.inv_eps_b = 1.0 / eb;
+      s.form = (so && so->formulation == GSM_FORM_H) ? FORM_H : FORM_E;
+      s.par.conv_a = s.form == FORM_H ? -eb : 1.0 / eb;
+      s.par.conv_b = s.form == FORM_H ? 1.0 : -1.0;
       double nn = 0;
       for (int c = 0; c < 3; ++c) {
         double re, im;
@@ -447,6 +527,7 @@ void build_groups(const std::vector<SysDesc>& sys, std::vector<Group>& groups, i
         sh.N1[a] = 2 * s.M[a] + 1;
       }
       sh.P = s.P;
+      sh.form = s.form;
       sh.npencil = sh.N1[0] * sh.N1[1];
       sh.n = 3LL * sh.npencil * sh.N1[2];
       sh.tstride = (sh.npencil + 63) / 64 * 64;
@@ -584,8 +665,8 @@ int carve_aux(const gsm_plan_s* plan, std::vector<Group>& groups, const std::vec
 
 // ------------------------------------------------------------ plan grids --
 
-int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** out) {
-  std::array<int, 4> key{M[0], M[1], M[2], P};
+int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** out, int kind = FORM_E) {
+  std::array<int, 5> key{M[0], M[1], M[2], P, kind};
   auto it = plan->grids.find(key);
   if (it != plan->grids.end()) {
     *out = &it->second;
@@ -602,7 +683,16 @@ int ensure_grid(gsm_plan_s* plan, const int M[3], int P, hipStream_t st, Grid** 
   HIP_TRY(dev_malloc(&t1, std::max((long long)P * nb[1] * nb[2], P3) * sizeof(double2)));
   HIP_TRY(dev_malloc(&t2, P3 * sizeof(double2)));
   const int off[3] = {2 * plan->mmax[0] - 2 * M[0], 2 * plan->mmax[1] - 2 * M[1], 2 * plan->mmax[2] - 2 * M[2]};
-  HIP_TRY(launch_copy_block(plan->d_coef, blk, plan->nc, nb, off, st));
+  const double2* src = kind == FORM_H ? plan->d_coef_inv : plan->d_coef;
+  if (!src) {
+    hipFree(g.g64);
+    hipFree(g.g32);
+    hipFree(blk);
+    hipFree(t1);
+    hipFree(t2);
+    return fail(GSM_E_ARG, "the plan holds no inverse-permittivity coefficients (the H-field system needs them)");
+  }
+  HIP_TRY(launch_copy_block(src, blk, plan->nc, nb, off, st));
   // x: blk[nz][ny][nbx] -> t1[nz][ny][P]
   HIP_TRY(launch_dft_axis(blk, t1, nb[2] * nb[1], nb[0], P, 1, -2 * M[0], 0, P, +1, st));
   // y: t1[nz][nby][P] -> t2[nz][P][P]
@@ -1470,7 +1560,7 @@ int solve_all(gsm_plan_s* plan, std::vector<SysDesc>& sys, std::vector<Group>& g
   std::vector<const Grid*> grids(groups.size());
   for (size_t i = 0; i < groups.size(); ++i) {
     Grid* grid = nullptr;
-    if ((rc = ensure_grid(plan, groups[i].shape.M, groups[i].shape.P, st, &grid))) return rc;
+    if ((rc = ensure_grid(plan, groups[i].shape.M, groups[i].shape.P, st, &grid, groups[i].shape.form))) return rc;
     rc = fp64 ? tune_families<double>(plan, groups[i], grid, so->restart, st)
               : tune_families<float>(plan, groups[i], grid, so->restart, st);
     if (rc) return rc;
@@ -1501,6 +1591,225 @@ void fill_info(const std::vector<SysDesc>& sys, const std::vector<SysExport>& ex
 
 int set_device(const gsm_plan_s* plan) {
   HIP_TRY(hipSetDevice(plan->device));
+  return GSM_OK;
+}
+
+// ------------------------------------------------------------ pole search --
+
+int check_pole_query(const gsm_pole_query& q, const int* mmax, int i) {
+  if (!std::isfinite(q.wavelength) || !(q.wavelength > 0)) return fail(GSM_E_ARG, "query %d: wavelength", i);
+  double kk = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(q.k_hat[a])) return fail(GSM_E_NONFINITE, "query %d: k_hat not finite", i);
+    kk += q.k_hat[a] * q.k_hat[a];
+    if (q.M[a] < 0 || q.M[a] > mmax[a]) return fail(GSM_E_ARG, "query %d: M[%d]=%d outside the plan", i, a, q.M[a]);
+  }
+  if (!(kk > 0)) return fail(GSM_E_ARG, "query %d: k_hat is zero", i);
+  if (q.n_poles < 1 || q.n_poles > GSM_POLE_MAX_NP)
+    return fail(GSM_E_ARG, "query %d: n_poles=%d outside [1, %d]", i, q.n_poles, GSM_POLE_MAX_NP);
+  if (q.n_div <= q.n_poles || q.n_div > GSM_POLE_MAX_ND)
+    return fail(GSM_E_ARG, "query %d: n_div=%d must exceed n_poles and be <= %d", i, q.n_div, GSM_POLE_MAX_ND);
+  if (q.component < 0 || q.component > 2) return fail(GSM_E_ARG, "query %d: component %d", i, q.component);
+  double nn = 0;
+  for (int c = 0; c < 6; ++c) {
+    if (!std::isfinite(q.pol[c])) return fail(GSM_E_NONFINITE, "query %d: pol not finite", i);
+    nn += q.pol[c] * q.pol[c];
+  }
+  if (nn == 0) return fail(GSM_E_ARG, "query %d: drive is zero", i);
+  if (!(std::isfinite(q.kappa_min) && std::isfinite(q.kappa_max) && q.kappa_min > 0 && q.kappa_max > q.kappa_min))
+    return fail(GSM_E_ARG, "query %d: need 0 < kappa_min < kappa_max", i);
+  if (!std::isfinite(q.eps_b)) return fail(GSM_E_NONFINITE, "query %d: eps_b not finite", i);
+  return GSM_OK;
+}
+
+// The N_d + N_p instances of a query's mesh (eps_b left to the caller).
+void pole_mesh(const gsm_pole_query& q, std::vector<gsm_instance>& out, std::vector<double>& kappa) {
+  const int npts = q.n_div + q.n_poles;
+  const double nk = std::sqrt(q.k_hat[0] * q.k_hat[0] + q.k_hat[1] * q.k_hat[1] + q.k_hat[2] * q.k_hat[2]);
+  for (int i = 0; i < npts; ++i) {
+    const double kap = q.kappa_min + (q.kappa_max - q.kappa_min) * i / (npts - 1);
+    gsm_instance in{};
+    in.wavelength = q.wavelength;
+    for (int a = 0; a < 3; ++a) {
+      in.k_inc[a] = kap * q.k_hat[a] / nk;
+      in.M[a] = q.M[a];
+    }
+    in.n_drive = 1;
+    for (int c = 0; c < 6; ++c) in.pol[0][c] = q.pol[c];
+    in.eps_b = 0;
+    out.push_back(in);
+    kappa.push_back(kap);
+  }
+}
+
+// One basis permittivity for a whole mesh (xi must be a single function of
+// kappa): see gsm_pole_query.
+int resolve_eps_b_mesh(const gsm_plan_s* plan, const gsm_instance* mesh, int n, double req, int qi, double* out) {
+  if (req > 0) {
+    for (int i = 0; i < n; ++i)
+      if (margin_scan(mesh[i], plan->period, req) < kSingularRel * req)
+        return fail(GSM_E_SINGULAR, "query %d: |k_m|^2 = k_b^2 within 1e-3 at mesh point %d for eps_b=%g", qi, i, req);
+    *out = req;
+    return GSM_OK;
+  }
+  bool ok = true;
+  for (int i = 0; i < n && ok; ++i) ok = margin_scan(mesh[i], plan->period, plan->eps_mean) >= kSingularRel * plan->eps_mean;
+  if (ok) {
+    *out = plan->eps_mean;
+    return GSM_OK;
+  }
+  std::vector<std::vector<double>> sh(n);
+  for (int i = 0; i < n; ++i) sh[i] = shell_values(mesh[i], plan->period);
+  const double lo = 0.5 * plan->eps_min, hi = 2.0 * plan->eps_max;
+  double best = -1, best_eb = plan->eps_mean;
+  const int ns = 4001;
+  for (int k = 0; k < ns; ++k) {
+    const double eb = lo + (hi - lo) * k / (ns - 1);
+    double r = INFINITY;
+    for (int i = 0; i < n; ++i) r = std::min(r, margin_of(sh[i], eb) / eb);
+    if (r > best) {
+      best = r;
+      best_eb = eb;
+    }
+  }
+  if (best < kSingularRel) return fail(GSM_E_SINGULAR, "query %d: no admissible eps_b for the whole mesh", qi);
+  *out = best_eb;
+  return GSM_OK;
+}
+
+// Buffers of a pole search after the groups' solve buffers: the mesh fields
+// and the fit's inputs and outputs (base == nullptr: size only).
+struct PoleBufs {
+  double2* E = nullptr;
+  long long* idx = nullptr;
+  double* kappa = nullptr;
+  double* xi = nullptr;
+  double* eta = nullptr;
+  double* zeta = nullptr;
+  int* status = nullptr;
+};
+size_t pole_layout(const std::vector<SysDesc>& sys, long long n_eta, int n_q, char* base, PoleBufs* out) {
+  long long total = 0;
+  for (auto& s : sys) total += s.n;
+  const long long ns = (long long)sys.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off += align256(std::max<size_t>(bytes, 1));
+    return (void*)q;
+  };
+  PoleBufs b;
+  b.E = (double2*)take(total * sizeof(double2));
+  b.idx = (long long*)take(ns * sizeof(long long));
+  b.kappa = (double*)take(ns * sizeof(double));
+  b.xi = (double*)take(2 * ns * sizeof(double));
+  b.eta = (double*)take(2 * n_eta * sizeof(double));
+  b.zeta = (double*)take(2 * n_eta * sizeof(double));
+  b.status = (int*)take(std::max(n_q, 1) * sizeof(int));
+  if (out) *out = b;
+  return off;
+}
+
+// Mesh instances of every query (basis permittivity resolved per query),
+// the systems and groups of one batched solve.
+int pole_systems(gsm_plan_s* p, int n_q, const gsm_pole_query* q, const gsm_solver_opts* so,
+                 std::vector<gsm_instance>& mesh, std::vector<double>& kappa, std::vector<double>& eb_q,
+                 std::vector<SysDesc>& sys, std::vector<Group>& groups) {
+  int rc;
+  for (int i = 0; i < n_q; ++i)
+    if ((rc = check_pole_query(q[i], p->mmax, i))) return rc;
+  eb_q.assign(n_q, 0.0);
+  for (int i = 0; i < n_q; ++i) {
+    const size_t first = mesh.size();
+    pole_mesh(q[i], mesh, kappa);
+    if ((rc = resolve_eps_b_mesh(p, mesh.data() + first, (int)(mesh.size() - first), q[i].eps_b, i, &eb_q[i])))
+      return rc;
+    for (size_t k = first; k < mesh.size(); ++k) mesh[k].eps_b = eb_q[i];
+  }
+  if ((rc = build_systems(p, (int)mesh.size(), mesh.data(), so, false, sys))) return rc;
+  build_groups(sys, groups, so->group_max);
+  return GSM_OK;
+}
+
+// Common start of every plan (voxel, shape or coefficient body): device,
+// options, tuning cache, periods and order ranges.  The caller fills the
+// coefficients and the permittivity statistics.
+int plan_begin(const gsm_plan_opts* opts, const double period[3], gsm_plan_s** out) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GSM_E_DEVICE, "no HIP device");
+  if (opts->device < 0 || opts->device >= ndev) return fail(GSM_E_ARG, "device %d not present", opts->device);
+  auto* p = new gsm_plan_s();
+  p->device = opts->device;
+  p->autotune = (opts->flags & GSM_PLAN_AUTOTUNE) != 0;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, opts->device) == hipSuccess) {
+      p->arch = prop.gcnArchName;
+      const size_t colon = p->arch.find(':');
+      if (colon != std::string::npos) p->arch.resize(colon);
+    }
+    if (p->arch.empty()) p->arch = "unknown";
+  }
+  if (opts->tune_cache) {
+    p->tune_cache = opts->tune_cache;
+    read_tune_cache(p);
+  }
+  for (int a = 0; a < 3; ++a) {
+    p->period[a] = period[a];
+    p->mmax[a] = opts->m_max[a];
+    p->nc[a] = 4 * opts->m_max[a] + 1;
+  }
+  int rc;
+  if ((rc = set_device(p))) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return GSM_OK;
+}
+
+// One operator application for the systems of one group: gather their
+// vectors from the caller's flat layout into the group's staging vector,
+// passes A, B and C, scatter the results back.  Synchronises the stream.
+int apply_group(Group& g, const std::vector<SysDesc>& sys, const Grid* grid, bool dbl, int mode, const void* x,
+                void* y, hipStream_t st) {
+  int rc;
+  const size_t eb = dbl ? sizeof(double2) : sizeof(float2);
+  std::vector<SysParam> par;
+  for (int si : g.sys) par.push_back(sys[si].par);
+  HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
+  for (int k = 0; k < g.shape.S; ++k) {
+    const SysDesc& s = sys[g.sys[k]];
+    HIP_TRY(hipMemcpyAsync((char*)g.x64 + k * g.shape.n * eb, (const char*)x + s.out_off * eb, s.n * eb,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  const int pa_mode = mode == GSM_APPLY_ADJOINT ? PA_GREEN_PRE : 0;
+  const int pc_mode = mode == GSM_APPLY_ADJOINT ? PC_ADJ : PC_FWD;
+  if (dbl) {
+    PassArgs<double> a = pass_args<double>(g, grid);
+    a.g.nblk_c = nblk_c_for(g.shape, true);
+    a.x = g.x64;
+    a.y = g.r64;
+    a.xs = a.ys = g.shape.n;
+    a.mode = pc_mode;
+    a.gate = GATE_NONE;
+    if ((rc = apply_passes<double>(a, pa_mode, st, g.shape.S))) return rc;
+  } else {
+    PassArgs<float> a = pass_args<float>(g, grid);
+    a.g.nblk_c = nblk_c_for(g.shape, false);
+    a.x = (float2*)g.x64;
+    a.y = (float2*)g.r64;
+    a.xs = a.ys = g.shape.n;
+    a.mode = pc_mode;
+    a.gate = GATE_NONE;
+    if ((rc = apply_passes<float>(a, pa_mode, st, g.shape.S))) return rc;
+  }
+  for (int k = 0; k < g.shape.S; ++k) {
+    const SysDesc& s = sys[g.sys[k]];
+    HIP_TRY(hipMemcpyAsync((char*)y + s.out_off * eb, (const char*)g.r64 + k * g.shape.n * eb, s.n * eb,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
   return GSM_OK;
 }
 
@@ -1542,6 +1851,7 @@ void gsm_solver_opts_default(gsm_solver_opts* o) {
   o->flags = 0;
   o->x0 = nullptr;
   o->group_max = 32;
+  o->formulation = GSM_FORM_E;
 }
 
 int gsm_fft_size(const int32_t M[3]) {
@@ -1588,31 +1898,10 @@ int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out
   int rc;
   if (!out) return fail(GSM_E_ARG, "out is NULL");
   if ((rc = check_geometry(geo)) || (rc = check_plan_opts(opts))) return rc;
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(GSM_E_DEVICE, "no HIP device");
-  if (opts->device < 0 || opts->device >= ndev) return fail(GSM_E_ARG, "device %d not present", opts->device);
-  auto* p = new gsm_plan_s();
-  p->device = opts->device;
-  p->autotune = (opts->flags & GSM_PLAN_AUTOTUNE) != 0;
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, opts->device) == hipSuccess) {
-      p->arch = prop.gcnArchName;
-      const size_t colon = p->arch.find(':');
-      if (colon != std::string::npos) p->arch.resize(colon);
-    }
-    if (p->arch.empty()) p->arch = "unknown";
-  }
-  if (opts->tune_cache) {
-    p->tune_cache = opts->tune_cache;
-    read_tune_cache(p);
-  }
-  for (int a = 0; a < 3; ++a) {
-    p->period[a] = geo->period[a];
-    p->vox[a] = geo->nvox[a];
-    p->mmax[a] = opts->m_max[a];
-    p->nc[a] = 4 * opts->m_max[a] + 1;
-  }
+  gsm_plan_s* p = nullptr;
+  if ((rc = plan_begin(opts, geo->period, &p))) return rc;
+  for (int a = 0; a < 3; ++a) p->vox[a] = geo->nvox[a];
+  p->voxel_body = true;
   const long long nv = (long long)p->vox[0] * p->vox[1] * p->vox[2];
   double s = 0, mn = INFINITY, mx = 0;
   for (long long i = 0; i < nv; ++i) {
@@ -1627,7 +1916,6 @@ int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out
     gsm_plan_destroy(p);
     return code;
   };
-  if ((rc = set_device(p))) return cleanup(rc);
   double* d_eps = nullptr;
   double2 *a = nullptr, *b = nullptr;
   const long long ncx = p->nc[0], ncy = p->nc[1], ncz = p->nc[2];
@@ -1637,6 +1925,7 @@ int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out
   if (e == hipSuccess) e = dev_malloc(&a, na * sizeof(double2));
   if (e == hipSuccess) e = dev_malloc(&b, nb * sizeof(double2));
   if (e == hipSuccess) e = dev_malloc(&p->d_coef, ncx * ncy * ncz * sizeof(double2));
+  if (e == hipSuccess) e = dev_malloc(&p->d_coef_inv, ncx * ncy * ncz * sizeof(double2));
   if (e != hipSuccess) {
     hipFree(d_eps);
     hipFree(a);
@@ -1644,24 +1933,133 @@ int gsm_plan(const gsm_geometry* geo, const gsm_plan_opts* opts, gsm_plan_t* out
     return cleanup(fail(GSM_E_NOMEM, "plan allocation: %s", hipGetErrorString(e)));
   }
   hipStream_t st = nullptr;
-  auto run = [&]() -> int {
-    HIP_TRY(hipMemcpy(d_eps, geo->eps, nv * sizeof(double), hipMemcpyHostToDevice));
+  // the exact image of a piecewise-constant voxel body: of eps (Eq.(4)) and
+  // of 1/eps (Eq.(5))
+  std::vector<double> inv(nv);
+  for (long long i = 0; i < nv; ++i) inv[i] = 1.0 / geo->eps[i];
+  auto image = [&](const double* host, double2* coef) -> int {
+    HIP_TRY(hipMemcpy(d_eps, host, nv * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(launch_real_to_complex(d_eps, a, nv, st));
     // voxel DFT along x: a[vz][vy][vx] -> b[vz][vy][ncx], n = j - 2 m_max
     HIP_TRY(launch_dft_axis(a, b, p->vox[2] * p->vox[1], p->vox[0], (int)ncx, 1, 0, -2 * p->mmax[0], p->vox[0], -1, st));
     // along y: b[vz][vy][ncx] -> a[vz][ncy][ncx]
     HIP_TRY(launch_dft_axis(b, a, p->vox[2], p->vox[1], (int)ncy, (int)ncx, 0, -2 * p->mmax[1], p->vox[1], -1, st));
     // along z: a[vz][ncy*ncx] -> coef[ncz][ncy*ncx]
-    HIP_TRY(launch_dft_axis(a, p->d_coef, 1, p->vox[2], (int)ncz, (int)(ncy * ncx), 0, -2 * p->mmax[2], p->vox[2], -1, st));
-    HIP_TRY(launch_box_factor(p->d_coef, p->nc, p->vox, st));
+    HIP_TRY(launch_dft_axis(a, coef, 1, p->vox[2], (int)ncz, (int)(ncy * ncx), 0, -2 * p->mmax[2], p->vox[2], -1, st));
+    HIP_TRY(launch_box_factor(coef, p->nc, p->vox, st));
     HIP_TRY(hipStreamSynchronize(st));
     return GSM_OK;
   };
-  rc = run();
+  rc = image(geo->eps, p->d_coef);
+  if (!rc) rc = image(inv.data(), p->d_coef_inv);
   hipFree(d_eps);
   hipFree(a);
   hipFree(b);
   if (rc) return cleanup(rc);
+  *out = p;
+  return GSM_OK;
+}
+
+int gsm_plan_shapes(const gsm_shape_body* body, const gsm_plan_opts* opts, gsm_plan_t* out) {
+  int rc;
+  if (!out) return fail(GSM_E_ARG, "out is NULL");
+  if ((rc = check_shape_body(body)) || (rc = check_plan_opts(opts))) return rc;
+  gsm_plan_s* p = nullptr;
+  if ((rc = plan_begin(opts, body->period, &p))) return rc;
+  auto cleanup = [&](int code) {
+    gsm_plan_destroy(p);
+    return code;
+  };
+  // permittivity statistics: the mean is c_0 (host plus each inclusion's
+  // contrast times its volume fraction), the range spans host and inclusions
+  const double cell = body->period[0] * body->period[1] * body->period[2];
+  double mean = body->eps_host, mn = body->eps_host, mx = body->eps_host;
+  std::vector<ShapeDesc> sd(body->n_shapes);
+  for (int k = 0; k < body->n_shapes; ++k) {
+    const gsm_shape& sh = body->shapes[k];
+    ShapeDesc& d = sd[k];
+    d.kind = sh.kind == GSM_SHAPE_BOX ? SHAPE_BOX : (sh.kind == GSM_SHAPE_SPHERE ? SHAPE_SPHERE : SHAPE_ELLIPSOID);
+    d.pad = 0;
+    for (int a = 0; a < 3; ++a) {
+      d.centre[a] = sh.centre[a];
+      d.size[a] = sh.kind == GSM_SHAPE_SPHERE ? sh.size[0] : sh.size[a];
+    }
+    d.weight = sh.eps - body->eps_host;
+    const double vol = d.kind == SHAPE_BOX ? 8.0 * d.size[0] * d.size[1] * d.size[2]
+                                           : 4.0 * M_PI / 3.0 * d.size[0] * d.size[1] * d.size[2];
+    mean += d.weight * vol / cell;
+    mn = std::min(mn, sh.eps);
+    mx = std::max(mx, sh.eps);
+  }
+  p->eps_mean = mean;
+  p->eps_min = mn;
+  p->eps_max = mx;
+  const long long ncn = (long long)p->nc[0] * p->nc[1] * p->nc[2];
+  ShapeDesc* d_sh = nullptr;
+  hipError_t e = dev_malloc(&p->d_coef, ncn * sizeof(double2));
+  if (e == hipSuccess) e = dev_malloc(&p->d_coef_inv, ncn * sizeof(double2));
+  if (e == hipSuccess) e = dev_malloc(&d_sh, 2 * std::max<size_t>(sd.size(), 1) * sizeof(ShapeDesc));
+  if (e != hipSuccess) {
+    hipFree(d_sh);
+    return cleanup(fail(GSM_E_NOMEM, "plan allocation: %s", hipGetErrorString(e)));
+  }
+  // the same shapes weighted by 1/eps_i - 1/eps_h give the image of 1/eps
+  std::vector<ShapeDesc> all = sd;
+  for (int k = 0; k < body->n_shapes; ++k) {
+    ShapeDesc d = sd[k];
+    d.weight = 1.0 / body->shapes[k].eps - 1.0 / body->eps_host;
+    all.push_back(d);
+  }
+  const int nsh = (int)sd.size();
+  auto run = [&]() -> int {
+    if (!all.empty()) HIP_TRY(hipMemcpy(d_sh, all.data(), all.size() * sizeof(ShapeDesc), hipMemcpyHostToDevice));
+    HIP_TRY(launch_shape_image(p->d_coef, p->nc, p->period, body->eps_host, d_sh, nsh, nullptr));
+    HIP_TRY(launch_shape_image(p->d_coef_inv, p->nc, p->period, 1.0 / body->eps_host, d_sh + nsh, nsh, nullptr));
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    return GSM_OK;
+  };
+  rc = run();
+  hipFree(d_sh);
+  if (rc) return cleanup(rc);
+  *out = p;
+  return GSM_OK;
+}
+
+int gsm_plan_from_coeffs(const gsm_coeff_body* body, const gsm_plan_opts* opts, gsm_plan_t* out) {
+  int rc;
+  if (!out) return fail(GSM_E_ARG, "out is NULL");
+  if ((rc = check_plan_opts(opts)) || (rc = check_coeff_body(body, opts))) return rc;
+  gsm_plan_s* p = nullptr;
+  if ((rc = plan_begin(opts, body->period, &p))) return rc;
+  auto cleanup = [&](int code) {
+    gsm_plan_destroy(p);
+    return code;
+  };
+  const int sx = 2 * body->n_max[0] + 1, sy = 2 * body->n_max[1] + 1;
+  p->eps_mean = body->coef[2 * (((long long)body->n_max[2] * sy + body->n_max[1]) * sx + body->n_max[0])];
+  p->eps_min = body->eps_min;
+  p->eps_max = body->eps_max;
+  // the |n_a| <= 2 m_max block of the caller's arrays, gathered on the host
+  const long long ncn = (long long)p->nc[0] * p->nc[1] * p->nc[2];
+  auto take = [&](const double* from, double2** to) -> int {
+    std::vector<double> blk(2 * ncn);
+    for (int z = 0; z < p->nc[2]; ++z)
+      for (int y = 0; y < p->nc[1]; ++y)
+        for (int x = 0; x < p->nc[0]; ++x) {
+          const long long src = ((long long)(z - 2 * p->mmax[2] + body->n_max[2]) * sy +
+                                 (y - 2 * p->mmax[1] + body->n_max[1])) * sx +
+                                (x - 2 * p->mmax[0] + body->n_max[0]);
+          const long long dst = ((long long)z * p->nc[1] + y) * p->nc[0] + x;
+          blk[2 * dst] = from[2 * src];
+          blk[2 * dst + 1] = from[2 * src + 1];
+        }
+    if (dev_malloc(to, ncn * sizeof(double2)) != hipSuccess) return fail(GSM_E_NOMEM, "plan allocation failed");
+    if (hipMemcpy(*to, blk.data(), ncn * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(GSM_E_DEVICE, "copy of the coefficients failed");
+    return GSM_OK;
+  };
+  if ((rc = take(body->coef, &p->d_coef))) return cleanup(rc);
+  if (body->coef_inv && (rc = take(body->coef_inv, &p->d_coef_inv))) return cleanup(rc);
   *out = p;
   return GSM_OK;
 }
@@ -1674,6 +2072,7 @@ int gsm_plan_destroy(gsm_plan_t p) {
     hipFree(kv.second.g32);
   }
   hipFree(p->d_coef);
+  hipFree(p->d_coef_inv);
   for (auto& sl : p->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
     if (sl.h_flags) hipHostFree(sl.h_flags);
@@ -1710,7 +2109,7 @@ int gsm_plan_tuning(gsm_plan_t p, const int32_t M[3], int32_t precision, int32_t
   const int d = precision == GSM_FP64 ? 1 : 0;
   int f[4];
   int t = 0;
-  auto g = p->grids.find({M[0], M[1], M[2], P});
+  auto g = p->grids.find({M[0], M[1], M[2], P, FORM_E});
   if (g != p->grids.end()) {
     for (int k = 0; k < 4; ++k) f[k] = g->second.fam[d][k];
     t = g->second.tuned[d];
@@ -1733,6 +2132,16 @@ int gsm_plan_coefficients(gsm_plan_t p, double* c_out) {
   if ((rc = set_device(p))) return rc;
   const long long n = (long long)p->nc[0] * p->nc[1] * p->nc[2];
   HIP_TRY(hipMemcpy(c_out, p->d_coef, n * sizeof(double2), hipMemcpyDeviceToHost));
+  return GSM_OK;
+}
+
+int gsm_plan_inverse_coefficients(gsm_plan_t p, double* c_out) {
+  if (!p || !c_out) return fail(GSM_E_ARG, "NULL argument");
+  if (!p->d_coef_inv) return fail(GSM_E_ARG, "the plan holds no inverse-permittivity coefficients");
+  int rc;
+  if ((rc = set_device(p))) return rc;
+  const long long n = (long long)p->nc[0] * p->nc[1] * p->nc[2];
+  HIP_TRY(hipMemcpy(c_out, p->d_coef_inv, n * sizeof(double2), hipMemcpyDeviceToHost));
   return GSM_OK;
 }
 
@@ -1807,59 +2216,24 @@ int gsm_apply(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t pr
               const void* x, void* y, void* ws, size_t ws_bytes, void* stream) {
   if (!p || !inst || n_inst < 1 || !x || !y) return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
   if (precision != GSM_FP64 && precision != GSM_MIXED) return fail(GSM_E_ARG, "unknown precision");
-  if (mode != GSM_APPLY_FORWARD && mode != GSM_APPLY_ADJOINT) return fail(GSM_E_ARG, "unknown mode");
+  if (mode != GSM_APPLY_FORWARD && mode != GSM_APPLY_ADJOINT && mode != GSM_APPLY_FORWARD_H)
+    return fail(GSM_E_ARG, "unknown mode");
   int rc;
   if ((rc = set_device(p))) return rc;
   gsm_solver_opts so;
   gsm_solver_opts_default(&so);
   so.precision = precision;
+  so.formulation = mode == GSM_APPLY_FORWARD_H ? GSM_FORM_H : GSM_FORM_E;
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, &so, false, sys))) return rc;
   std::vector<Group> groups;
   build_groups(sys, groups, 0);  // one pass: nothing to overlap, and never more groups than the workspace query
   if ((rc = carve(groups, ws, ws_bytes, so.restart, precision == GSM_FP64))) return rc;
   hipStream_t st = (hipStream_t)stream;
-  const bool dbl = precision == GSM_FP64;
-  const size_t eb = dbl ? sizeof(double2) : sizeof(float2);
   for (auto& g : groups) {
     Grid* grid = nullptr;
-    if ((rc = ensure_grid(p, g.shape.M, g.shape.P, st, &grid))) return rc;
-    std::vector<SysParam> par;
-    for (int si : g.sys) par.push_back(sys[si].par);
-    HIP_TRY(hipMemcpyAsync(g.par, par.data(), par.size() * sizeof(SysParam), hipMemcpyHostToDevice, st));
-    // gather inputs into the group's staging vectors (x64 slot), outputs to r64 slot
-    for (int k = 0; k < g.shape.S; ++k) {
-      const SysDesc& s = sys[g.sys[k]];
-      HIP_TRY(hipMemcpyAsync((char*)g.x64 + k * g.shape.n * eb, (const char*)x + s.out_off * eb, s.n * eb,
-                             hipMemcpyDeviceToDevice, st));
-    }
-    const int pa_mode = mode == GSM_APPLY_ADJOINT ? PA_GREEN_PRE : 0;
-    const int pc_mode = mode == GSM_APPLY_ADJOINT ? PC_ADJ : PC_FWD;
-    if (dbl) {
-      PassArgs<double> a = pass_args<double>(g, grid);
-      a.g.nblk_c = nblk_c_for(g.shape, true);
-      a.x = g.x64;
-      a.y = g.r64;
-      a.xs = a.ys = g.shape.n;
-      a.mode = pc_mode;
-      a.gate = GATE_NONE;
-      if ((rc = apply_passes<double>(a, pa_mode, st, g.shape.S))) return rc;
-    } else {
-      PassArgs<float> a = pass_args<float>(g, grid);
-      a.g.nblk_c = nblk_c_for(g.shape, false);
-      a.x = (float2*)g.x64;
-      a.y = (float2*)g.r64;
-      a.xs = a.ys = g.shape.n;
-      a.mode = pc_mode;
-      a.gate = GATE_NONE;
-      if ((rc = apply_passes<float>(a, pa_mode, st, g.shape.S))) return rc;
-    }
-    for (int k = 0; k < g.shape.S; ++k) {
-      const SysDesc& s = sys[g.sys[k]];
-      HIP_TRY(hipMemcpyAsync((char*)y + s.out_off * eb, (const char*)g.r64 + k * g.shape.n * eb, s.n * eb,
-                             hipMemcpyDeviceToDevice, st));
-    }
-    HIP_TRY(hipStreamSynchronize(st));
+    if ((rc = ensure_grid(p, g.shape.M, g.shape.P, st, &grid, g.shape.form))) return rc;
+    if ((rc = apply_group(g, sys, grid, precision == GSM_FP64, mode, x, y, st))) return rc;
   }
   return GSM_OK;
 }
@@ -1870,6 +2244,8 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
   if (!p || !inst || n_inst < 1 || !eps_eff || !info) return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
   int rc;
   if ((rc = check_solver_opts(so))) return rc;
+  if (so->formulation != GSM_FORM_E)
+    return fail(GSM_E_ARG, "the effective tensor D0 E0^-1 is defined on the E-field system (formulation E)");
   if ((rc = set_device(p))) return rc;
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, so, true, sys))) return rc;
@@ -1922,6 +2298,153 @@ int gsm_eff_tensor(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, const
       }
   }
   return worst;
+}
+
+int gsm_pole_workspace_size(gsm_plan_t p, int32_t n_q, const gsm_pole_query* q, const gsm_solver_opts* so,
+                            size_t* bytes) {
+  if (!p || !q || n_q < 1 || !bytes) return fail(GSM_E_ARG, "NULL argument or n_q < 1");
+  gsm_solver_opts d;
+  if (!so) {
+    gsm_solver_opts_default(&d);
+    so = &d;
+  }
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  std::vector<gsm_instance> mesh;
+  std::vector<double> kappa, eb;
+  std::vector<SysDesc> sys;
+  std::vector<Group> groups;
+  if ((rc = pole_systems(p, n_q, q, so, mesh, kappa, eb, sys, groups))) return rc;
+  long long n_eta = 0;
+  for (int i = 0; i < n_q; ++i) n_eta += q[i].n_poles;
+  *bytes = workspace_for(groups, so->restart, so->precision == GSM_FP64) + pole_layout(sys, n_eta, n_q, nullptr, nullptr);
+  return GSM_OK;
+}
+
+int gsm_pole_search(gsm_plan_t p, int32_t n_q, const gsm_pole_query* q, const gsm_solver_opts* so, void* ws,
+                    size_t ws_bytes, gsm_pole_result* out, void* stream) {
+  if (!p || !q || n_q < 1 || !out) return fail(GSM_E_ARG, "NULL argument or n_q < 1");
+  int rc;
+  if ((rc = check_solver_opts(so))) return rc;
+  if ((rc = set_device(p))) return rc;
+  std::vector<gsm_instance> mesh;
+  std::vector<double> kappa, eb;
+  std::vector<SysDesc> sys;
+  std::vector<Group> groups;
+  if ((rc = pole_systems(p, n_q, q, so, mesh, kappa, eb, sys, groups))) return rc;
+  long long n_eta = 0;
+  for (int i = 0; i < n_q; ++i) n_eta += q[i].n_poles;
+  const size_t gbytes = workspace_for(groups, so->restart, so->precision == GSM_FP64);
+  const size_t need = gbytes + pole_layout(sys, n_eta, n_q, nullptr, nullptr);
+  if (!ws) return fail(GSM_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(GSM_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  // the groups' buffers come first (gbytes includes 256 bytes of alignment slack)
+  char* base = (char*)(((uintptr_t)ws + 255) & ~uintptr_t(255)) + (gbytes - 256);
+  PoleBufs b;
+  pole_layout(sys, n_eta, n_q, base, &b);
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<SysExport> exp;
+  gsm_solver_opts so2 = *so;
+  so2.flags &= ~GSM_OUT_HOST;
+  so2.x0 = nullptr;
+  if ((rc = solve_all(p, sys, groups, &so2, ws, ws_bytes, (double*)b.E, false, exp, st))) return rc;
+  // xi_i: the chosen component of each mesh field's zeroth harmonic
+  std::vector<long long> idx(sys.size());
+  size_t si = 0;
+  for (int i = 0; i < n_q; ++i) {
+    const int npts = q[i].n_div + q[i].n_poles;
+    for (int k = 0; k < npts; ++k, ++si) {
+      const SysDesc& s = sys[si];
+      const long long n1x = 2 * s.M[0] + 1, n1y = 2 * s.M[1] + 1, n1z = 2 * s.M[2] + 1;
+      const long long i0 = ((long long)s.M[2] * n1y + s.M[1]) * n1x + s.M[0];
+      idx[si] = s.out_off + (long long)q[i].component * n1x * n1y * n1z + i0;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(b.idx, idx.data(), idx.size() * sizeof(long long), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b.kappa, kappa.data(), kappa.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_gather_zero_order(b.E, b.idx, b.xi, (int)sys.size(), st));
+  // one fit launch per run of consecutive queries with equal (N_p, N_d)
+  long long pt = 0, et = 0;
+  for (int i = 0; i < n_q;) {
+    int j = i;
+    while (j < n_q && q[j].n_poles == q[i].n_poles && q[j].n_div == q[i].n_div) ++j;
+    PoleFitArgs fa{};
+    fa.n = j - i;
+    fa.n_poles = q[i].n_poles;
+    fa.n_div = q[i].n_div;
+    fa.kappa = b.kappa + pt;
+    fa.xi = b.xi + 2 * pt;
+    fa.eta = b.eta + 2 * et;
+    fa.zeta = b.zeta + 2 * et;
+    fa.status = b.status + i;
+    HIP_TRY(launch_pole_fit(fa, st));
+    pt += (long long)(j - i) * (q[i].n_div + q[i].n_poles);
+    et += (long long)(j - i) * q[i].n_poles;
+    i = j;
+  }
+  std::vector<double> eta(2 * n_eta), zeta(2 * n_eta);
+  std::vector<int> fst(n_q);
+  HIP_TRY(hipMemcpyAsync(eta.data(), b.eta, eta.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(zeta.data(), b.zeta, zeta.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(fst.data(), b.status, n_q * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int worst = GSM_OK;
+  si = 0;
+  et = 0;
+  for (int i = 0; i < n_q; ++i) {
+    gsm_pole_result r{};
+    const int npts = q[i].n_div + q[i].n_poles, Np = q[i].n_poles;
+    r.status = GSM_OK;
+    r.n_poles = Np;
+    r.eps_b = eb[i];
+    for (int k = 0; k < npts; ++k, ++si) {
+      if (exp[si].status != 0) r.status = GSM_W_NOT_CONVERGED;
+      r.iterations += exp[si].iters;
+      r.max_rel_residual = std::max(r.max_rel_residual, exp[si].rel);
+    }
+    if (fst[i] != GSM_OK) r.status = fst[i];
+    const double k0 = 2.0 * M_PI / q[i].wavelength;
+    r.best = -1;
+    double bz = -1;
+    for (int k = 0; k < Np; ++k) {
+      for (int c = 0; c < 2; ++c) {
+        r.eta[k][c] = eta[2 * (et + k) + c];
+        r.zeta[k][c] = zeta[2 * (et + k) + c];
+      }
+      const double az = std::hypot(r.zeta[k][0], r.zeta[k][1]);
+      if (fst[i] == GSM_OK && r.eta[k][0] >= q[i].kappa_min && r.eta[k][0] <= q[i].kappa_max && az > bz) {
+        bz = az;
+        r.best = k;
+      }
+    }
+    r.n_eff = r.best >= 0 ? r.eta[r.best][0] / k0 : 0.0;
+    et += Np;
+    out[i] = r;
+    if (r.status < 0 && (worst >= 0 || r.status < worst)) worst = r.status;
+    if (r.status > 0 && worst == GSM_OK) worst = r.status;
+  }
+  return worst;
+}
+
+int gsm_pole_fit(int32_t n, int32_t n_poles, int32_t n_div, const double* kappa, const double* xi, double* eta,
+                 double* zeta, int32_t* status, void* stream) {
+  if (n < 0) return fail(GSM_E_ARG, "n < 0");
+  if (n_poles < 1 || n_poles > GSM_POLE_MAX_NP) return fail(GSM_E_ARG, "n_poles=%d outside [1, %d]", n_poles, GSM_POLE_MAX_NP);
+  if (n_div <= n_poles || n_div > GSM_POLE_MAX_ND)
+    return fail(GSM_E_ARG, "n_div=%d must exceed n_poles and be <= %d", n_div, GSM_POLE_MAX_ND);
+  if (n == 0) return GSM_OK;
+  if (!kappa || !xi || !eta || !zeta || !status) return fail(GSM_E_ARG, "NULL argument");
+  PoleFitArgs fa{};
+  fa.n = n;
+  fa.n_poles = n_poles;
+  fa.n_div = n_div;
+  fa.kappa = kappa;
+  fa.xi = xi;
+  fa.eta = eta;
+  fa.zeta = zeta;
+  fa.status = status;
+  HIP_TRY(launch_pole_fit(fa, (hipStream_t)stream));
+  return GSM_OK;
 }
 
 int gsm_profile_begin(void) { return gsm_profile_begin_sampled(nullptr, 1); }
@@ -1984,6 +2507,7 @@ int gsm_solve_adjoint(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, co
     return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
   int rc;
   if ((rc = check_solver_opts(so))) return rc;
+  if (so->formulation != GSM_FORM_E) return fail(GSM_E_ARG, "the adjoint solve is built for the E-field system");
   if ((rc = set_device(p))) return rc;
   std::vector<SysDesc> sys;
   if ((rc = build_systems(p, n_inst, inst, so, false, sys))) return rc;
@@ -2029,8 +2553,11 @@ int gsm_eff_tensor_vjp(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, c
                        size_t ws_bytes, gsm_solve_info* info, void* stream) {
   if (!p || !inst || n_inst < 1 || !E_save || !eps_eff || !gbar || !grad_vox || !info)
     return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  if (!p->voxel_body)
+    return fail(GSM_E_ARG, "the plan was made from shapes or coefficients: it has no voxels to differentiate by");
   int rc;
   if ((rc = check_solver_opts(so))) return rc;
+  if (so->formulation != GSM_FORM_E) return fail(GSM_E_ARG, "the gradient is built for the E-field system");
   if ((rc = set_device(p))) return rc;
   hipStream_t st = (hipStream_t)stream;
   std::vector<SysDesc> sys;

@@ -35,6 +35,10 @@ struct SysParam {
   int max_iter;
   int max_refine;
   int pad[2];
+  // the plane pass multiplies by conv_a g(r) + conv_b: g = eps, (1/eps_b, -1)
+  // for Eq.(4); g = 1/eps, (-eps_b, 1) for Eq.(5)
+  double conv_a;
+  double conv_b;
 };
 
 // Per-system solver state (device memory).
@@ -84,7 +88,10 @@ struct GroupShape {
   long long tsize;  // 3 * tstride * P complex values per system (intermediate)
   int nchunk;       // ceil(n / kGsChunk)
   int nblk_c;       // pass C blocks per system
+  int form;         // FORM_E: the E-field system of Eq.(4); FORM_H: the H-field system of Eq.(5)
+  int reserved;     // zero (no padding bytes in kernel arguments)
 };
+enum { FORM_E = 0, FORM_H = 1 };
 
 // pass A modes
 enum { PA_NORMALIZE = 1, PA_GREEN_PRE = 2 };
@@ -184,5 +191,34 @@ hipError_t launch_extract_grid(const double2* in, double* g64, float* g32, long 
                                hipStream_t s);
 hipError_t launch_copy_block(const double2* src, double2* dst, const int src_n[3],
                              const int dst_n[3], const int off[3], hipStream_t s);
+// ---- pole search (poles.hip) ----
+struct PoleFitArgs {
+  int n;              // problems
+  int n_poles;        // N_p
+  int n_div;          // N_d
+  int pad;
+  const double* kappa;  // [n][N_d + N_p] mesh
+  const double* xi;     // [n][N_d + N_p] complex samples (re, im)
+  double* eta;          // [n][N_p] complex poles, ascending real part
+  double* zeta;         // [n][N_p] complex amplitudes
+  int* status;          // [n] GSM_OK or GSM_E_SINGULAR
+};
+hipError_t launch_pole_fit(const PoleFitArgs& a, hipStream_t s);
+hipError_t launch_gather_zero_order(const double2* E, const long long* idx, double* xi, int n, hipStream_t s);
+
+// one inclusion of an analytic body: kind, centre, radius / semi-axes /
+// half-sides, and its weight in the image (eps_i - eps_h, or the difference
+// of the inverses)
+enum { SHAPE_SPHERE = 0, SHAPE_ELLIPSOID = 1, SHAPE_BOX = 2 };
+struct ShapeDesc {
+  int kind;
+  int pad;
+  double centre[3];
+  double size[3];
+  double weight;
+};
+// c[nz][ny][nx] (dims nc, index n + (nc-1)/2) = host delta_n0 + sum_k weight_k S_k(G_n)
+hipError_t launch_shape_image(double2* c, const int nc[3], const double period[3], double host,
+                              const ShapeDesc* sh, int nsh, hipStream_t s);
 
 }  // namespace gsm

@@ -1,3 +1,5 @@
-// plan-time kernels and the adjoint of the effective-tensor retrieval
+// plan-time kernels, the adjoint of the effective-tensor retrieval and the
+// pole search
 #include "plan.inc"
 #include "adjoint.inc"
+#include "poles.inc"

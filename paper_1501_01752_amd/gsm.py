@@ -19,7 +19,8 @@ GSM_E_SINGULAR, GSM_E_WORKSPACE, GSM_E_UNSUPPORTED = -5, -6, -7
 GSM_MIXED, GSM_FP64 = 0, 1
 GSM_GMRES, GSM_BICGSTAB = 0, 1
 GSM_OUT_HOST, GSM_SOLVE_GRAPH = 1, 2
-GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT = 0, 1
+GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT, GSM_APPLY_FORWARD_H = 0, 1, 2
+GSM_FORM_E, GSM_FORM_H = 0, 1
 GSM_PLAN_AUTOTUNE = 1
 
 
@@ -41,7 +42,82 @@ class SolverOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("inner_tol", C.c_double), ("restart", C.c_int32),
                 ("max_iter", C.c_int32), ("max_refine", C.c_int32), ("precision", C.c_int32),
                 ("method", C.c_int32), ("flags", C.c_int32), ("x0", C.c_void_p),
-                ("group_max", C.c_int32), ("reserved", C.c_int32)]
+                ("group_max", C.c_int32), ("formulation", C.c_int32)]
+
+
+GSM_SHAPE_SPHERE, GSM_SHAPE_ELLIPSOID, GSM_SHAPE_BOX = 0, 1, 2
+_SHAPE_KINDS = {"sphere": GSM_SHAPE_SPHERE, "ellipsoid": GSM_SHAPE_ELLIPSOID, "box": GSM_SHAPE_BOX}
+
+
+class Shape(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("centre", C.c_double * 3),
+                ("size", C.c_double * 3), ("eps", C.c_double)]
+
+
+class ShapeBody(C.Structure):
+    _fields_ = [("period", C.c_double * 3), ("eps_host", C.c_double), ("n_shapes", C.c_int32),
+                ("reserved", C.c_int32), ("shapes", C.POINTER(Shape))]
+
+
+class CoeffBody(C.Structure):
+    _fields_ = [("period", C.c_double * 3), ("n_max", C.c_int32 * 3), ("reserved", C.c_int32),
+                ("coef", C.POINTER(C.c_double)), ("eps_min", C.c_double), ("eps_max", C.c_double),
+                ("coef_inv", C.POINTER(C.c_double))]
+
+
+GSM_POLE_MAX_NP, GSM_POLE_MAX_ND = 8, 32
+
+
+class PoleQuery(C.Structure):
+    _fields_ = [("wavelength", C.c_double), ("k_hat", C.c_double * 3), ("M", C.c_int32 * 3),
+                ("n_poles", C.c_int32), ("n_div", C.c_int32), ("component", C.c_int32),
+                ("pol", C.c_double * 6), ("kappa_min", C.c_double), ("kappa_max", C.c_double),
+                ("eps_b", C.c_double)]
+
+
+class PoleResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_poles", C.c_int32), ("best", C.c_int32),
+                ("iterations", C.c_int32), ("eta", (C.c_double * 2) * GSM_POLE_MAX_NP),
+                ("zeta", (C.c_double * 2) * GSM_POLE_MAX_NP), ("n_eff", C.c_double),
+                ("eps_b", C.c_double), ("max_rel_residual", C.c_double)]
+
+    def as_dict(self):
+        n = self.n_poles
+        return {"status": self.status, "n_poles": n, "best": self.best, "iterations": self.iterations,
+                "eta": np.array([complex(self.eta[k][0], self.eta[k][1]) for k in range(n)]),
+                "zeta": np.array([complex(self.zeta[k][0], self.zeta[k][1]) for k in range(n)]),
+                "n_eff": self.n_eff, "eps_b": self.eps_b, "max_rel_residual": self.max_rel_residual}
+
+
+def make_pole_query(wavelength, k_hat, M, kappa_min, kappa_max, drive=(1.0, 0.0, 0.0), component=0,
+                    n_poles=5, n_div=10, eps_b=0.0):
+    """One pole search along k_hat with the given drive: xi = E_component,0."""
+    q = PoleQuery()
+    q.wavelength = float(wavelength)
+    for a in range(3):
+        q.k_hat[a] = float(k_hat[a])
+        q.M[a] = int(M[a])
+        z = complex(drive[a])
+        q.pol[2 * a], q.pol[2 * a + 1] = z.real, z.imag
+    q.n_poles, q.n_div, q.component = int(n_poles), int(n_div), int(component)
+    q.kappa_min, q.kappa_max, q.eps_b = float(kappa_min), float(kappa_max), float(eps_b)
+    return q
+
+
+def pole_fit(kappa, xi, n_poles, n_div, stream=None):
+    """gsm_pole_fit on device tensors: kappa float64 [n, N_d+N_p], xi
+    complex128 [n, N_d+N_p] -> (eta, zeta complex128 [n, N_p], status int32 [n])."""
+    import torch
+    kappa = kappa.contiguous()
+    xi = xi.contiguous()
+    n = kappa.shape[0]
+    eta = torch.empty((n, n_poles), dtype=torch.complex128, device=kappa.device)
+    zeta = torch.empty_like(eta)
+    status = torch.empty(n, dtype=torch.int32, device=kappa.device)
+    _check(lib().gsm_pole_fit(n, n_poles, n_div, C.c_void_p(kappa.data_ptr()), C.c_void_p(xi.data_ptr()),
+                              C.c_void_p(eta.data_ptr()), C.c_void_p(zeta.data_ptr()),
+                              C.c_void_p(status.data_ptr()), _stream(stream)))
+    return eta, zeta, status
 
 
 class SolveInfo(C.Structure):
@@ -77,7 +153,10 @@ _SIGS = {
     "gsm_basis_eps": (C.c_int, [C.c_void_p, C.POINTER(Instance), C.POINTER(C.c_double)]),
     "gsm_plan": (C.c_int, [C.POINTER(Geometry), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
     "gsm_plan_destroy": (C.c_int, [C.c_void_p]),
+    "gsm_plan_shapes": (C.c_int, [C.POINTER(ShapeBody), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
+    "gsm_plan_from_coeffs": (C.c_int, [C.POINTER(CoeffBody), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]),
     "gsm_plan_coefficients": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gsm_plan_inverse_coefficients": (C.c_int, [C.c_void_p, C.c_void_p]),
     "gsm_plan_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gsm_plan_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int32)]),
@@ -99,6 +178,12 @@ _SIGS = {
                                      C.c_void_p, C.c_void_p, C.c_size_t, C.POINTER(SolveInfo),
                                      C.c_void_p]),
     "gsm_allocation_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gsm_pole_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(PoleQuery),
+                                          C.POINTER(SolverOpts), C.POINTER(C.c_size_t)]),
+    "gsm_pole_search": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(PoleQuery), C.POINTER(SolverOpts),
+                                  C.c_void_p, C.c_size_t, C.POINTER(PoleResult), C.c_void_p]),
+    "gsm_pole_fit": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsm_profile_begin": (C.c_int, []),
     "gsm_profile_begin_only": (C.c_int, [C.c_char_p]),
     "gsm_profile_begin_sampled": (C.c_int, [C.c_char_p, C.c_int32]),
@@ -218,17 +303,12 @@ def _stream(stream):
 
 
 class Plan:
-    """Owning handle of a gsm_plan_t built from a voxel body."""
+    """Owning handle of a gsm_plan_t built from a voxel body (the default),
+    or from an analytic shape body (Plan.from_shapes) or given Fourier
+    coefficients (Plan.from_coeffs)."""
 
     def __init__(self, eps, period=(1.0, 1.0, 1.0), m_max=(15, 15, 15), device=0, autotune=False,
-                 tune_cache=None):
-        self.eps = np.ascontiguousarray(eps, dtype=np.float64)
-        vz, vy, vx = self.eps.shape
-        g = Geometry()
-        for a in range(3):
-            g.period[a] = float(period[a])
-        g.nvox[0], g.nvox[1], g.nvox[2] = vx, vy, vz
-        g.eps = self.eps.ctypes.data_as(C.POINTER(C.c_double))
+                 tune_cache=None, _body=None):
         o = PlanOpts()
         for a in range(3):
             o.m_max[a] = int(m_max[a])
@@ -237,12 +317,64 @@ class Plan:
         self._tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
         o.tune_cache = self._tune_cache
         h = C.c_void_p()
-        _check(lib().gsm_plan(C.byref(g), C.byref(o), C.byref(h)), allow_warn=False)
+        if _body is None:
+            self.eps = np.ascontiguousarray(eps, dtype=np.float64)
+            vz, vy, vx = self.eps.shape
+            g = Geometry()
+            for a in range(3):
+                g.period[a] = float(period[a])
+            g.nvox[0], g.nvox[1], g.nvox[2] = vx, vy, vz
+            g.eps = self.eps.ctypes.data_as(C.POINTER(C.c_double))
+            _check(lib().gsm_plan(C.byref(g), C.byref(o), C.byref(h)), allow_warn=False)
+        else:
+            kind, body = _body
+            fn = lib().gsm_plan_shapes if kind == "shapes" else lib().gsm_plan_from_coeffs
+            _check(fn(C.byref(body), C.byref(o), C.byref(h)), allow_warn=False)
         self.handle = h
         self.m_max = tuple(int(m) for m in m_max)
         self.period = tuple(float(p) for p in period)
         self.device = device
         self._ws = None
+
+    @classmethod
+    def from_shapes(cls, period, eps_host, shapes, m_max=(15, 15, 15), device=0, autotune=False,
+                    tune_cache=None):
+        """Plan of a host eps_host with inclusions: shapes are dicts
+        {"kind": "sphere" | "ellipsoid" | "box", "centre": (x, y, z),
+        "size": radius | semi-axes | half-sides, "eps": value}."""
+        arr = (Shape * max(len(shapes), 1))()
+        for i, sh in enumerate(shapes):
+            arr[i].kind = _SHAPE_KINDS[sh["kind"]]
+            size = np.broadcast_to(np.asarray(sh["size"], dtype=np.float64), (3,))
+            for a in range(3):
+                arr[i].centre[a] = float(sh["centre"][a])
+                arr[i].size[a] = float(size[a])
+            arr[i].eps = float(sh["eps"])
+        b = ShapeBody()
+        for a in range(3):
+            b.period[a] = float(period[a])
+        b.eps_host = float(eps_host)
+        b.n_shapes = len(shapes)
+        b.shapes = arr
+        return cls(None, period, m_max, device, autotune, tune_cache, _body=("shapes", b))
+
+    @classmethod
+    def from_coeffs(cls, period, coef, eps_min, eps_max, m_max=(15, 15, 15), device=0, autotune=False,
+                    tune_cache=None, coef_inv=None):
+        """Plan from Fourier coefficients c_n, a complex array of shape
+        (2Nz+1, 2Ny+1, 2Nx+1) indexed n + N (N_a >= 2 m_max[a]); coef_inv
+        (same layout), the coefficients of 1/eps, enables the H system."""
+        c = np.ascontiguousarray(coef, dtype=np.complex128)
+        ci = None if coef_inv is None else np.ascontiguousarray(coef_inv, dtype=np.complex128)
+        b = CoeffBody()
+        b.coef_inv = None if ci is None else ci.ctypes.data_as(C.POINTER(C.c_double))
+        for a in range(3):
+            b.period[a] = float(period[a])
+        b.n_max[0], b.n_max[1], b.n_max[2] = ((c.shape[2] - 1) // 2, (c.shape[1] - 1) // 2,
+                                              (c.shape[0] - 1) // 2)
+        b.coef = c.ctypes.data_as(C.POINTER(C.c_double))
+        b.eps_min, b.eps_max = float(eps_min), float(eps_max)
+        return cls(None, period, m_max, device, autotune, tune_cache, _body=("coeffs", b))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -273,6 +405,13 @@ class Plan:
         n = [4 * m + 1 for m in self.m_max]
         out = np.zeros((n[2], n[1], n[0]), dtype=np.complex128)
         _check(lib().gsm_plan_coefficients(self.handle, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def inverse_coefficients(self):
+        """Coefficients of 1/eps (the H-field system's), layout of coefficients()."""
+        n = [4 * m + 1 for m in self.m_max]
+        out = np.zeros((n[2], n[1], n[0]), dtype=np.complex128)
+        _check(lib().gsm_plan_inverse_coefficients(self.handle, out.ctypes.data_as(C.c_void_p)))
         return out
 
     def contrast_grid(self, M, P):
@@ -329,6 +468,21 @@ class Plan:
                                C.c_void_p(y.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
                                _stream(stream)))
         return y
+
+    def pole_search(self, queries, opts=None, stream=None):
+        """Mesh solves and pole fit of every query (gsm_pole_search); returns
+        (list of result dicts, status)."""
+        import torch
+        opts = opts or default_opts()
+        arr = (PoleQuery * len(queries))(*queries)
+        nb = C.c_size_t()
+        _check(lib().gsm_pole_workspace_size(self.handle, len(queries), arr, C.byref(opts), C.byref(nb)))
+        ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        out = (PoleResult * len(queries))()
+        st = lib().gsm_pole_search(self.handle, len(queries), arr, C.byref(opts), C.c_void_p(ws.data_ptr()),
+                                   ws.numel(), out, _stream(stream))
+        _check(st)
+        return [r.as_dict() for r in out], st
 
     def solve_adjoint(self, insts, rhs, opts=None, stream=None):
         """lambda = A^-H rhs for every (instance, drive); rhs complex128 (device)."""

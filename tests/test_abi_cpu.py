@@ -43,7 +43,7 @@ def test_solver_opts_layout_matches_the_library():
     o = gsm.SolverOpts.from_buffer_copy(bytes(buf[:size]))
     assert (o.tol, o.inner_tol, o.restart, o.max_iter, o.max_refine) == (1e-9, 1e-5, 30, 5000, 200)
     assert (o.precision, o.method, o.flags) == (gsm.GSM_MIXED, gsm.GSM_GMRES, 0)
-    assert not o.x0 and o.group_max == 32 and o.reserved == 0
+    assert not o.x0 and o.group_max == 32 and o.formulation == gsm.GSM_FORM_E
 
 
 def test_strerror_and_defaults():
@@ -183,3 +183,61 @@ def test_light_cone_check_matches_every_harmonic():
             assert _validate(g, po, [inst]) == want, (t, eb)
             checked += want == gsm.GSM_E_SINGULAR
     assert checked > 300  # the shell cases really hit the band
+
+
+def _shape_body(shapes, period=(1.0, 1.0, 1.0), eps_host=1.0):
+    arr = (gsm.Shape * max(len(shapes), 1))()
+    for i, (kind, centre, size, eps) in enumerate(shapes):
+        arr[i].kind = kind
+        for a in range(3):
+            arr[i].centre[a] = centre[a]
+            arr[i].size[a] = size[a]
+        arr[i].eps = eps
+    b = gsm.ShapeBody()
+    for a in range(3):
+        b.period[a] = period[a]
+    b.eps_host, b.n_shapes, b.shapes = eps_host, len(shapes), arr
+    return b, arr
+
+
+def test_shape_plan_argument_errors_without_device():
+    """gsm_plan_shapes checks its body before it touches a device."""
+    L = gsm.lib()
+    h = C.c_void_p()
+    ok = (gsm.GSM_SHAPE_SPHERE, (0.5, 0.5, 0.5), (0.3, 0, 0), 4.0)
+    for bad, code in [((7, (0.5, 0.5, 0.5), (0.3, 0, 0), 4.0), gsm.GSM_E_ARG),          # kind
+                      ((gsm.GSM_SHAPE_SPHERE, (0.5, 0.5, 0.5), (0.6, 0, 0), 4.0), gsm.GSM_E_ARG),  # 1.2 > period
+                      ((gsm.GSM_SHAPE_BOX, (0.5, 0.5, 0.5), (0.2, 0.0, 0.2), 4.0), gsm.GSM_E_ARG),  # zero side
+                      ((gsm.GSM_SHAPE_ELLIPSOID, (0.5, np.nan, 0.5), (0.2, 0.1, 0.2), 4.0), gsm.GSM_E_NONFINITE),
+                      ((gsm.GSM_SHAPE_SPHERE, (0.5, 0.5, 0.5), (0.3, 0, 0), -1.0), gsm.GSM_E_ARG)]:
+        b, keep = _shape_body([ok, bad])
+        assert L.gsm_plan_shapes(C.byref(b), C.byref(_popts()), C.byref(h)) == code
+    b, keep = _shape_body([ok], eps_host=0.0)
+    assert L.gsm_plan_shapes(C.byref(b), C.byref(_popts()), C.byref(h)) == gsm.GSM_E_ARG
+
+
+def test_coefficient_plan_argument_errors_without_device():
+    """gsm_plan_from_coeffs refuses too few orders and the image of a
+    permittivity that is not real, before it touches a device."""
+    from oracle import gsm as O
+    L = gsm.lib()
+    h = C.c_void_p()
+    vox = np.random.default_rng(3).uniform(1, 4, (3, 4, 5))
+
+    def body(c, emin=1.0, emax=4.0):
+        c = np.ascontiguousarray(c, dtype=np.complex128)
+        b = gsm.CoeffBody()
+        b.period[0] = b.period[1] = b.period[2] = 1.0
+        b.n_max[0], b.n_max[1], b.n_max[2] = (c.shape[2] - 1) // 2, (c.shape[1] - 1) // 2, (c.shape[0] - 1) // 2
+        b.coef = c.ctypes.data_as(C.POINTER(C.c_double))
+        b.eps_min, b.eps_max = emin, emax
+        return b, c
+
+    b, keep = body(O.box_image(vox, (5, 5, 5)))                       # 5 < 2 m_max = 6
+    assert L.gsm_plan_from_coeffs(C.byref(b), C.byref(_popts()), C.byref(h)) == gsm.GSM_E_ARG
+    c = O.box_image(vox, (6, 6, 6))
+    c[7, 6, 6] += 0.1j                                                 # no longer Hermitian
+    b, keep = body(c)
+    assert L.gsm_plan_from_coeffs(C.byref(b), C.byref(_popts()), C.byref(h)) == gsm.GSM_E_ARG
+    b, keep = body(O.box_image(vox, (6, 6, 6)), emin=3.0, emax=2.0)
+    assert L.gsm_plan_from_coeffs(C.byref(b), C.byref(_popts()), C.byref(h)) == gsm.GSM_E_ARG
