@@ -328,6 +328,28 @@ int gsm_solve(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst,
 int gsm_apply(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst, int32_t precision,
               int32_t mode, const void* x, void* y, void* ws, size_t ws_bytes, void* stream);
 
+/* gsm_apply without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments, kernels and results as
+ * gsm_apply; the intermediate buffers (per-system parameters, the staged
+ * input and output vectors, the FFT pass planes) live instead in a static
+ * device array of GSM_APPLY_STATIC_BYTES that the library holds on each
+ * device it runs on until the process ends.  The call allocates no device
+ * or pinned memory: it never calls hipMalloc or hipFree.
+ * - Limit: the systems of one (M, P) group must fit in the array; a larger
+ *   call fails with GSM_E_WORKSPACE (split it).  At M = 15 that is about
+ *   ten systems in complex128 or twenty in complex64.
+ * - The contrast grid of each (M, P) used must already exist on the plan
+ *   (made by any earlier gsm_apply, gsm_solve, gsm_eff_tensor or
+ *   gsm_plan_contrast_grid with those orders); otherwise GSM_E_ARG.
+ * - Every call on one device shares that device's array: calls that overlap
+ *   on one device (several host threads or streams) race and must be
+ *   serialised by the caller.  The array keeps the last call's contents.
+ * Synchronises `stream` before returning, like gsm_apply. */
+#define GSM_APPLY_STATIC_BYTES ((size_t)64 << 20)
+int gsm_apply_static(gsm_plan_t plan, int32_t n_inst, const gsm_instance* inst, int32_t precision,
+                     int32_t mode, const void* x, void* y, void* stream);
+
 /* Effective permittivity tensor of each instance (field-averaged form): the
  * three drives a = x, y, z are solved, and with E0 and D0 the zeroth Fourier
  * orders of E and of eps E, eps_eff = D0 E0^-1 (3x3 complex128, row-major,

@@ -24,6 +24,11 @@
 
 using namespace gsm;
 
+// Scratch memory of the allocation-free operator application
+// (gsm_apply_static), 64 MiB per device, held until the process ends.
+constexpr size_t kScratchBytes = GSM_APPLY_STATIC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -1813,6 +1818,52 @@ int apply_group(Group& g, const std::vector<SysDesc>& sys, const Grid* grid, boo
   return GSM_OK;
 }
 
+// ---------------------------------------------- allocation-free apply ----
+// gsm_apply_static takes its buffers from this array instead of a caller
+// workspace.  On the host the array's name only stands in for the device
+// symbol: no kernel argument, copy or fill ever names it.  Each device's
+// address of its copy is looked up once, with that device current, and kept
+// in g_scratch_ptr.  Only the forward and adjoint applications use it, and
+// they read nothing of it before writing it, so it is never cleared.
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kScratchDevices] = {};
+
+int static_scratch(int device, char** out) {
+  if (device < 0 || device >= kScratchDevices)
+    return fail(GSM_E_UNSUPPORTED, "gsm_apply_static: device ordinal %d beyond %d", device, kScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;  // the caller has made `device` current
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(GSM_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return GSM_OK;
+}
+
+// Buffers of one group's operator application carved from base (nullptr:
+// size only): parameters, the staged input and output vectors, the pass
+// intermediate.
+size_t layout_apply(Group& g, char* base, size_t eb) {
+  const long long S = g.shape.S, n = g.shape.n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base ? base + off : nullptr;
+    off += align256(bytes);
+    return (void*)q;
+  };
+  g.par = (SysParam*)take(S * sizeof(SysParam));
+  g.x64 = (double2*)take(S * n * eb);
+  g.r64 = (double2*)take(S * n * eb);
+  g.T = (double2*)take(S * g.shape.tsize * eb);
+  g.st = nullptr;  // not read without gating or basis scaling
+  g.partc = nullptr;  // written only in the residual modes
+  return off;
+}
+
 }  // namespace
 
 // ===================================================================== ABI ==
@@ -2234,6 +2285,52 @@ int gsm_apply(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t pr
     Grid* grid = nullptr;
     if ((rc = ensure_grid(p, g.shape.M, g.shape.P, st, &grid, g.shape.form))) return rc;
     if ((rc = apply_group(g, sys, grid, precision == GSM_FP64, mode, x, y, st))) return rc;
+  }
+  return GSM_OK;
+}
+
+int gsm_apply_static(gsm_plan_t p, int32_t n_inst, const gsm_instance* inst, int32_t precision, int32_t mode,
+                     const void* x, void* y, void* stream) {
+  if (!p || !inst || n_inst < 1 || !x || !y) return fail(GSM_E_ARG, "NULL argument or n_inst < 1");
+  if (precision != GSM_FP64 && precision != GSM_MIXED) return fail(GSM_E_ARG, "unknown precision");
+  if (mode != GSM_APPLY_FORWARD && mode != GSM_APPLY_ADJOINT && mode != GSM_APPLY_FORWARD_H)
+    return fail(GSM_E_ARG, "unknown mode");
+  int rc;
+  if ((rc = set_device(p))) return rc;
+  char* base = nullptr;
+  if ((rc = static_scratch(p->device, &base))) return rc;
+  gsm_solver_opts so;
+  gsm_solver_opts_default(&so);
+  so.precision = precision;
+  so.formulation = mode == GSM_APPLY_FORWARD_H ? GSM_FORM_H : GSM_FORM_E;
+  std::vector<SysDesc> sys;
+  if ((rc = build_systems(p, n_inst, inst, &so, false, sys))) return rc;
+  std::vector<Group> groups;
+  build_groups(sys, groups, 0);
+  const bool dbl = precision == GSM_FP64;
+  const size_t eb = dbl ? sizeof(double2) : sizeof(float2);
+  // every group must fit on its own (groups run one after the other and each
+  // starts at the base of the array) and its contrast grid must exist already
+  std::vector<Grid*> grids;
+  for (auto& g : groups) {
+    const size_t need = layout_apply(g, nullptr, eb);
+    if (need > kScratchBytes)
+      return fail(GSM_E_WORKSPACE,
+                  "gsm_apply_static: %d systems at M = (%d, %d, %d) need %zu bytes of scratch, the static array "
+                  "holds %zu (split the call)",
+                  g.shape.S, g.shape.M[0], g.shape.M[1], g.shape.M[2], need, kScratchBytes);
+    auto it = p->grids.find({g.shape.M[0], g.shape.M[1], g.shape.M[2], g.shape.P, g.shape.form});
+    if (it == p->grids.end())
+      return fail(GSM_E_ARG,
+                  "gsm_apply_static: the plan has no contrast grid for M = (%d, %d, %d), P = %d yet (one call of "
+                  "gsm_apply, gsm_solve or gsm_plan_contrast_grid with these orders makes it)",
+                  g.shape.M[0], g.shape.M[1], g.shape.M[2], g.shape.P);
+    grids.push_back(&it->second);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  for (size_t k = 0; k < groups.size(); ++k) {
+    layout_apply(groups[k], base, eb);
+    if ((rc = apply_group(groups[k], sys, grids[k], dbl, mode, x, y, st))) return rc;
   }
   return GSM_OK;
 }

@@ -167,6 +167,8 @@ _SIGS = {
                             C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(SolveInfo), C.c_void_p]),
     "gsm_apply": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.c_int32, C.c_int32,
                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "gsm_apply_static": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.c_int32, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]),
     "gsm_eff_tensor": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Instance), C.POINTER(SolverOpts),
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                  C.POINTER(SolveInfo), C.c_void_p]),
@@ -467,6 +469,25 @@ class Plan:
         _check(lib().gsm_apply(self.handle, len(insts), arr, precision, mode, C.c_void_p(x.data_ptr()),
                                C.c_void_p(y.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(),
                                _stream(stream)))
+        return y
+
+    def apply_static(self, insts, x, y=None, precision=GSM_FP64, mode=GSM_APPLY_FORWARD, stream=None):
+        """y = A x (or A^H x) through gsm_apply_static: no workspace, the
+        library's static scratch array instead.  y may be given (preallocated
+        by the caller); otherwise it is allocated here, outside the call."""
+        import torch
+        arr = instances_array(insts)
+        x = x.contiguous()
+        want = torch.complex128 if precision == GSM_FP64 else torch.complex64
+        if x.dtype != want:
+            raise TypeError(f"x must be {want}")
+        if y is None:
+            y = torch.empty_like(x)
+        elif y.dtype != want or y.numel() != x.numel() or not y.is_contiguous():
+            raise TypeError("y must be a contiguous tensor of x's dtype and size")
+        _check(lib().gsm_apply_static(self.handle, len(insts), arr, precision, mode,
+                                      C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                      _stream(stream)))
         return y
 
     def pole_search(self, queries, opts=None, stream=None):
