@@ -23,8 +23,10 @@ plain FP64 GPU solve of the same workload; the literal 4-solve case, the
 uneven 256-instance sweep, the 32^3-voxel inverse-design gradient and the
 M = 31 woodpile batch as further lines of the same JSON object; Table 1's
 single-solve workload at three sizes (context beside the paper's times); the
-achievable copy bandwidth; and the CPU oracle (scipy.fft on the host threads
-+ SciPy GMRES, FP64) timed on a bounded sample.
+achievable copy bandwidth; the pole search of Eqs.(6)-(10) on the paper's
+Fig. 2 lattices (E and H systems, beside the printed indices); the headline
+batch through the H-field system of Eq.(5); and the CPU oracle (scipy.fft
+on the host threads + SciPy GMRES, FP64) timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -72,6 +74,10 @@ def parse():
     ap.add_argument("--one-group-steps", type=int, default=None,
                     help="timed steps with one launch group per call, for the dominant kernel's own rate "
                          "(default: --steps; 0: skip)")
+    ap.add_argument("--pole-steps", type=int, default=2,
+                    help="timed rounds of the Fig. 2 pole searches (E and H systems, 0: skip)")
+    ap.add_argument("--hfield-steps", type=int, default=2,
+                    help="timed steps of the headline batch through the H-field system (0: skip)")
     ap.add_argument("--table1-reps", type=int, default=10,
                     help="timed single solves per size and precision of Table 1's workload (0: skip)")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -439,6 +445,100 @@ def table1(gsm, inputs, reps):
             "note": "paper_gpu_ms: the paper's Table 1 (FP64, its 2013 GPU, 16/32/64 harmonics per axis), context"}
 
 
+# Fig. 2 of the paper: cubic air cavities of side Lambda/2 in n = 1.5 and 3.0,
+# Lambda = 0.3 lambda; its printed (converged) effective indices, context
+FIG2_PAPER_NEFF = {2.25: 1.441688, 9.0: 2.82503}
+
+
+def pole_search(gsm, steps):
+    """The pole search of Eqs.(6)-(10) on Fig. 2's lattices at 31^3
+    harmonics (64^3 grid): per host permittivity, the E system (x drive,
+    xi = E_x,0) and the H system (y drive, xi = H_y,0) along z, N_p = 5,
+    N_d = 10 (15 mesh solves per query, complex64 + FP64 refinement to
+    1e-10), all four queries' 60 solves in two calls (one per system); wall
+    time per search and the effective indices beside the paper's."""
+    import torch
+    M = (15, 15, 15)
+    lam = 1 / 0.3
+    k0 = 2 * np.pi / lam
+    out = {"unit": "searches/s", "n_poles": 5, "n_div": 10, "harmonics": "31^3", "rows": []}
+    plans, queries = [], []
+    for eh, n_paper in FIG2_PAPER_NEFF.items():
+        vox = np.full((4, 4, 4), eh)
+        vox[1:3, 1:3, 1:3] = 1.0
+        plans.append(gsm.Plan(vox, (1.0, 1.0, 1.0), M))
+        lo, hi = (n_paper - 0.08) * k0, (n_paper + 0.08) * k0
+        queries.append((gsm.make_pole_query(lam, (0, 0, 1), M, lo, hi),
+                        gsm.make_pole_query(lam, (0, 0, 1), M, lo, hi, drive=(0, 1, 0), component=1)))
+    opts = {"E": gsm.default_opts(tol=1e-10), "H": gsm.default_opts(tol=1e-10, formulation=gsm.GSM_FORM_H)}
+    res = {}
+    for plan, (qe, qh) in zip(plans, queries):   # warm-up (grids, codelet tuning)
+        plan.pole_search([qe], opts["E"])
+        plan.pole_search([qh], opts["H"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for i, (plan, (qe, qh)) in enumerate(zip(plans, queries)):
+            res[(i, "E")] = plan.pole_search([qe], opts["E"])[0][0]
+            res[(i, "H")] = plan.pole_search([qh], opts["H"])[0][0]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for i, (eh, n_paper) in enumerate(FIG2_PAPER_NEFF.items()):
+        row = {"host_eps": eh, "paper_n_eff": n_paper}
+        for f in ("E", "H"):
+            r = res[(i, f)]
+            row[f"{f}_n_eff"] = r["n_eff"]
+            row[f"{f}_status"] = r["status"]
+            row[f"{f}_mesh_iterations"] = r["iterations"]
+            row[f"{f}_max_rel_residual"] = r["max_rel_residual"]
+        out["rows"].append(row)
+    n = 4 * steps
+    out["value"] = round(n / dt, 3)
+    out["ms_per_search"] = round(dt / n * 1e3, 3)
+    for p in plans:
+        p.close()
+    return out
+
+
+def hfield_solve(work, gsm, steps):
+    """The headline batch (both bodies, 128 solves) through the H-field
+    system of Eq.(5) (transverse H drives: the E drives rotated by k x),
+    complex64 + FP64 refinement to 1e-9: solves/s beside the E system's."""
+    import torch
+    opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30, formulation=gsm.GSM_FORM_H)
+    hw = []
+    for plan, insts in work:
+        hi = []
+        for inst in insts:
+            k = np.array([inst.k_inc[a] for a in range(3)])
+            kh = k / np.linalg.norm(k)
+            drives = []
+            for d in range(inst.n_drive):
+                a = np.array([complex(inst.pol[d][2 * c], inst.pol[d][2 * c + 1]) for c in range(3)])
+                drives.append(tuple(np.cross(kh, a)))
+            h = gsm.make_instance(inst.wavelength, k, [inst.M[a] for a in range(3)], drives)
+            h.eps_b = plan.basis_eps(h)
+            hi.append(h)
+        hw.append((plan, hi))
+    for plan, hi in hw:
+        plan.solve(hi, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n, worst, iters = 0, 0.0, 0
+    for _ in range(steps):
+        for plan, hi in hw:
+            _, info, st = plan.solve(hi, opts)
+            if st != gsm.GSM_OK:
+                raise RuntimeError(f"H-field solve status {st}")
+            n += len(info)
+            worst = max(worst, max(i["rel_residual"] for i in info))
+            iters += sum(i["iterations"] for i in info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 3), "unit": "solves/s", "solves_per_step": n // steps,
+            "max_rel_residual": worst, "mean_iterations": round(iters / n, 2)}
+
+
 def matvec_hbm(prof, prec="c64"):
     """The matrix-vector product as a whole (passes A, B and C of a profiled
     step): algorithmic bytes over the summed launch durations, against the
@@ -631,6 +731,8 @@ def main():
     design = inverse_design(gsm, inputs, args.design_steps) if args.design_steps > 0 else None
     wood = woodpile(gsm, inputs, args.woodpile_steps) if args.woodpile_steps > 0 else None
     tab1 = table1(gsm, inputs, args.table1_reps) if args.table1_reps > 0 else None
+    poles = pole_search(gsm, args.pole_steps) if args.pole_steps > 0 else None
+    hfield = hfield_solve(work, gsm, args.hfield_steps) if args.hfield_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     copy_bw = copy_bandwidth()
     per_step = total // args.steps
@@ -660,6 +762,8 @@ def main():
         "inverse_design": design,
         "woodpile": wood,
         "table1": tab1,
+        "pole_search": poles,
+        "hfield_solve": hfield,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
