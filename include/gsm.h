@@ -127,7 +127,7 @@ enum {
 };
 
 typedef struct gsm_plan_opts {
-  int32_t m_max[3];       /* largest order count M_a any instance will use (0..31) */
+  int32_t m_max[3];       /* largest order count M_a any instance will use (0..127) */
   int32_t device;         /* HIP device ordinal */
   int32_t flags;          /* GSM_PLAN_AUTOTUNE or 0 */
   int32_t reserved;       /* must be 0 */
@@ -191,7 +191,10 @@ void gsm_solver_opts_default(gsm_solver_opts* opts);
 
 /* FFT grid size P used for order counts M (the smallest supported size with
  * P >= 4 max_a M_a + 1, the condition under which the cropped FFT product
- * equals the truncated Toeplitz product).  Returns P > 0, or GSM_E_UNSUPPORTED. */
+ * equals the truncated Toeplitz product).  Supported: the powers of two 4 ..
+ * 512 (M up to 127, the paper's largest Table 1 size); from 256 on the plane
+ * pass runs as three kernels with the column-expanded planes in HBM (a plane
+ * no longer fits in LDS).  Returns P > 0, or GSM_E_UNSUPPORTED. */
 int gsm_fft_size(const int32_t M[3]);
 
 /* CPU-only validation of a geometry, plan options and instances (no device

@@ -262,6 +262,30 @@ def solve_fft_gmres(c, M, q, eps_b, a, P, rtol=1e-12, restart=30, maxiter=2000,
     return x.reshape(shape), count[0]
 
 
+def apply_operator_at(c, M, q, eps_b, x, orders):
+    """(A x)_m of Eq.(4) at the listed output orders m = (mx, my, mz) only,
+    each written out from the definition:
+    (A x)_m = x_m - G(q_m) sum_m' (c_{m-m'}/eps_b - delta_mm') x_m'.
+    One output costs a pass over all N inputs (for checks at sizes where the
+    whole product would not fit the host's time).  x: (3, N1z, N1y, N1x).
+    Returns (len(orders), 3)."""
+    x = np.asarray(x, dtype=np.complex128)
+    nz0 = (c.shape[0] - 1) // 2
+    ny0 = (c.shape[1] - 1) // 2
+    nx0 = (c.shape[2] - 1) // 2
+    mzs = np.arange(-M[2], M[2] + 1)[:, None, None]
+    mys = np.arange(-M[1], M[1] + 1)[None, :, None]
+    mxs = np.arange(-M[0], M[0] + 1)[None, None, :]
+    out = np.zeros((len(orders), 3), dtype=np.complex128)
+    for k, (mx, my, mz) in enumerate(orders):
+        cm = c[mz - mzs + nz0, my - mys + ny0, mx - mxs + nx0] / eps_b     # c_{m-m'}/eps_b over m'
+        w = np.array([np.sum(cm * x[comp]) for comp in range(3)])
+        w -= x[:, mz + M[2], my + M[1], mx + M[0]]                          # - delta_mm' x_m'
+        G = green_tensor(q[mz + M[2], my + M[1], mx + M[0]], eps_b)
+        out[k] = x[:, mz + M[2], my + M[1], mx + M[0]] - G @ w
+    return out
+
+
 def relative_residual(c, M, q, eps_b, a, E, P):
     """||b - A E||_2 / ||b||_2 over all 3N unknowns of Eq.(4)."""
     b = incident_rhs(M, a)

@@ -51,7 +51,7 @@ int fail(int code, const char* fmt, ...) {
                   #expr, hipGetErrorString(e_), __FILE__, __LINE__);                       \
   } while (0)
 
-constexpr int kSupportedP[] = {4, 8, 16, 32, 64, 128};
+constexpr int kSupportedP[] = {4, 8, 16, 32, 64, 128, 256, 512};
 
 int fft_size_for(const int32_t M[3]) {
   int mm = std::max(M[0], std::max(M[1], M[2]));
@@ -427,6 +427,7 @@ struct Group {
   double2* rhs64 = nullptr;  // general right-hand sides (adjoint solve)
   void* V = nullptr;
   double2* T = nullptr;
+  double2* U = nullptr;  // P >= 256: the plane pass's column-expanded planes
   double2* part1 = nullptr;
   double* partn = nullptr;
   double* partc = nullptr;
@@ -547,6 +548,12 @@ void build_groups(const std::vector<SysDesc>& sys, std::vector<Group>& groups, i
   for (auto& g : groups) g.shape.S = (int)g.sys.size();
 }
 
+// Complex values per system of the plane pass's intermediate U[c][z][y][mx]
+// on the grids whose planes do not fit in LDS (P >= 256), else 0.
+long long plane_split_size(const GroupShape& sh) {
+  return sh.P >= 256 ? 3LL * sh.P * sh.P * sh.N1[0] : 0;
+}
+
 // Carve one group's buffers from base (base == nullptr: size only).
 size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c) {
   const long long S = g.shape.S, n = g.shape.n;
@@ -564,6 +571,7 @@ size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c
   g.rhs64 = (double2*)take(S * n * sizeof(double2));
   g.V = take(S * (restart + 1) * n * vbytes);
   g.T = (double2*)take(S * g.shape.tsize * sizeof(double2));
+  g.U = (double2*)take(S * plane_split_size(g.shape) * sizeof(double2));
   g.part1 = (double2*)take(S * g.shape.nchunk * (restart + 2) * sizeof(double2));
   g.partn = (double*)take(S * g.shape.nchunk * sizeof(double));
   g.partc = (double*)take(S * nblk_c * sizeof(double));
@@ -777,6 +785,8 @@ PassArgs<T> pass_args(const Group& g, const Grid* grid) {
   a.grid = sizeof(T) == 8 ? (const T*)grid->g64 : (const T*)grid->g32;
   for (int k = 0; k < 4; ++k) a.fam[k] = grid->fam[sizeof(T) == 8 ? 1 : 0][k];
   a.partial = g.partc;
+  a.u = (cplx<T>*)g.U;
+  a.us = plane_split_size(g.shape);
   return a;
 }
 
@@ -948,8 +958,11 @@ int pmin_smooth(const int M[3]) {
 // in the reverse order.
 PassBytes pass_flops(const GroupShape& g) {
   const int lp = __builtin_ctz(g.P) - 2;
-  auto fe = [&](int ax) { return (double)kPrunedOps[lp][g.M[ax]][0]; };
-  auto fc = [&](int ax) { return (double)kPrunedOps[lp][g.M[ax]][1]; };
+  // beyond the generated table (P >= 256): the 5 P log2 P real operations of
+  // a full radix-2 transform, an upper estimate of the pruned one
+  const double full = 5.0 * g.P * (lp + 2);
+  auto fe = [&](int ax) { return lp < 6 ? (double)kPrunedOps[lp][g.M[ax]][0] : full; };
+  auto fc = [&](int ax) { return lp < 6 ? (double)kPrunedOps[lp][g.M[ax]][1] : full; };
   const double P = g.P, nx = g.N1[0], ny = g.N1[1], nz = g.N1[2];
   const double plane = ny * (fe(0) + fc(0)) + P * (fe(1) + fc(1)) + 2.0 * P * P;
   return {3.0 * nx * ny * fe(2), 3.0 * P * plane, 3.0 * nx * ny * fc(2) + 36.0 * nx * ny * nz};
@@ -1859,6 +1872,7 @@ size_t layout_apply(Group& g, char* base, size_t eb) {
   g.x64 = (double2*)take(S * n * eb);
   g.r64 = (double2*)take(S * n * eb);
   g.T = (double2*)take(S * g.shape.tsize * eb);
+  g.U = (double2*)take(S * plane_split_size(g.shape) * eb);
   g.st = nullptr;  // not read without gating or basis scaling
   g.partc = nullptr;  // written only in the residual modes
   return off;

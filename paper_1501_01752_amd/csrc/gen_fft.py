@@ -500,7 +500,7 @@ def main(path):
                 out.append(dispatch(fname, n, len(i), len(o), 'C', (len(o) - 1) // 2, family))
             else:
                 out.append(dispatch(fname, n, len(i), len(o), 'F', s, family))
-    for n in (8, 16, 32, 64, 128):
+    for n in (8, 16, 32, 64, 128, 512):
         out.append(twiddle_table(n))
     with open(path, 'w') as f:
         f.write('\n'.join(out))

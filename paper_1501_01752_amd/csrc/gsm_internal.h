@@ -9,7 +9,7 @@
 namespace gsm {
 
 constexpr int kMaxRestart = 64;   // largest Krylov dimension per cycle
-constexpr int kMaxOrder = 31;     // largest M_a (P = 128)
+constexpr int kMaxOrder = 127;    // largest M_a (P = 512)
 constexpr int kGsThreads = 256;   // block size of the Gram-Schmidt kernels
 #ifndef GSM_GS_PER_THREAD
 #define GSM_GS_PER_THREAD 8
@@ -120,6 +120,9 @@ struct PassArgs {
   hipEvent_t ev0, ev1;  // when set: stamped at the start and end of the launch
   int fam[4];           // codelet family per stage: pass A, pass B rows, pass B columns, pass C
   int xnorm;            // passes A and C read x scaled by the system's vscale
+  int pad;
+  cplx<T>* u;           // P >= 256: the plane pass's column-expanded planes [S][3][P][P][N1x]
+  long long us;         // per-system stride of u (complex values)
 };
 
 // ---- launchers (passes.hip) ----

@@ -56,14 +56,15 @@ def test_strerror_and_defaults():
 
 @pytest.mark.parametrize("M,P", [((0, 0, 0), 4), ((1, 1, 1), 8), ((3, 3, 3), 16), ((3, 1, 0), 16),
                                  ((7, 2, 2), 32), ((15, 15, 15), 64), ((16, 6, 6), 128),
-                                 ((31, 31, 31), 128)])
+                                 ((31, 31, 31), 128), ((32, 0, 0), 256), ((63, 63, 63), 256),
+                                 ((2, 64, 1), 512), ((127, 127, 127), 512)])
 def test_fft_size(M, P):
     assert gsm.fft_size(M) == P
     assert P >= 4 * max(M) + 1
 
 
 def test_fft_size_unsupported():
-    assert gsm.fft_size((32, 0, 0)) == gsm.GSM_E_UNSUPPORTED
+    assert gsm.fft_size((128, 0, 0)) == gsm.GSM_E_UNSUPPORTED
 
 
 def _geom(eps, period=(1.0, 1.0, 1.0)):
@@ -106,7 +107,7 @@ def test_validate_nan_voxel():
 def test_validate_bad_sizes():
     g, keep = _geom(np.full((4, 4, 4), 2.0), period=(1.0, -1.0, 1.0))
     assert _validate(g) == gsm.GSM_E_ARG
-    assert _validate(None, _popts((40, 0, 0))) == gsm.GSM_E_UNSUPPORTED
+    assert _validate(None, _popts((128, 0, 0))) == gsm.GSM_E_UNSUPPORTED
     g, keep = _geom(np.full((4, 4, 4), -2.0))
     assert _validate(g) == gsm.GSM_E_ARG
 

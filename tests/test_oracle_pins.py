@@ -97,3 +97,24 @@ def test_gradient_oracle_tensor_equals_schur_form():
     # the same tensor with another basis permittivity (eps_eff does not depend on it)
     ee2 = OG._fields_and_tensor(c, M, q, 6.1)[-1]
     assert np.abs(ee2 - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_operator_at_sampled_orders_equals_dense_matrix():
+    """The one-output-at-a-time form of Eq.(4) (for full-size checks) equals
+    the rows of the dense truncated matrix, which the pins above tie to
+    closed forms and an exact solution."""
+    import numpy as np
+    from oracle import gsm as O
+    rng = np.random.default_rng(8)
+    eps = rng.uniform(1.0, 5.0, (3, 4, 5))
+    M = (2, 3, 1)
+    c = O.box_image(eps, tuple(2 * m for m in M))
+    q = O.harmonic_q(np.array([0.4, -0.1, 1.3]), 1.0, (1.0, 0.9, 1.2), M)
+    x = rng.standard_normal((3, 3, 7, 5)) + 1j * rng.standard_normal((3, 3, 7, 5))
+    A = O.assemble_dense(c, M, q, 2.2)
+    y = (A @ x.ravel()).reshape(3, 3, 7, 5)
+    orders = [(0, 0, 0), (2, -3, 1), (-1, 2, -1), (-2, 0, 1)]
+    got = O.apply_operator_at(c, M, q, 2.2, x, orders)
+    for k, (mx, my, mz) in enumerate(orders):
+        ref = y[:, mz + M[2], my + M[1], mx + M[0]]
+        assert np.abs(got[k] - ref).max() <= 1e-13 * np.abs(y).max()
