@@ -51,7 +51,7 @@ int fail(int code, const char* fmt, ...) {
                   #expr, hipGetErrorString(e_), __FILE__, __LINE__);                       \
   } while (0)
 
-constexpr int kSupportedP[] = {4, 8, 16, 32, 64, 128, 256, 512};
+constexpr int kSupportedP[] = {4, 8, 16, 32, 36, 40, 48, 64, 72, 128, 256, 512};
 
 int fft_size_for(const int32_t M[3]) {
   int mm = std::max(M[0], std::max(M[1], M[2]));
@@ -957,12 +957,12 @@ int pmin_smooth(const int M[3]) {
 // harmonic).  Pass B expands x on N1y rows, then y on P columns, and crops
 // in the reverse order.
 PassBytes pass_flops(const GroupShape& g) {
-  const int lp = __builtin_ctz(g.P) - 2;
+  const int row = pruned_ops_row(g.P);
   // beyond the generated table (P >= 256): the 5 P log2 P real operations of
   // a full radix-2 transform, an upper estimate of the pruned one
-  const double full = 5.0 * g.P * (lp + 2);
-  auto fe = [&](int ax) { return lp < 6 ? (double)kPrunedOps[lp][g.M[ax]][0] : full; };
-  auto fc = [&](int ax) { return lp < 6 ? (double)kPrunedOps[lp][g.M[ax]][1] : full; };
+  const double full = 5.0 * g.P * std::log2((double)g.P);
+  auto fe = [&](int ax) { return row >= 0 ? (double)kPrunedOps[row][g.M[ax]][0] : full; };
+  auto fc = [&](int ax) { return row >= 0 ? (double)kPrunedOps[row][g.M[ax]][1] : full; };
   const double P = g.P, nx = g.N1[0], ny = g.N1[1], nz = g.N1[2];
   const double plane = ny * (fe(0) + fc(0)) + P * (fe(1) + fc(1)) + 2.0 * P * P;
   return {3.0 * nx * ny * fe(2), 3.0 * P * plane, 3.0 * nx * ny * fc(2) + 36.0 * nx * ny * nz};

@@ -430,6 +430,25 @@ def crop_slots(n, k):
     return list(range(n)), [x % n for x in range(-k, k + 1)]
 
 
+# FFT grid sizes of the pass kernels: the powers of two, and between 32 and
+# 128 the 2-3-smooth sizes whose pruned transforms (and lane splits) cost
+# less than the next power of two for the order counts they serve: 36
+# (M = 8), 40 (M = 9), 48 (M = 10, 11), 72 (M = 16, 17).  Sizes with a
+# factor 5 or an odd lane length cost more operations than 64 (50, 54, 60).
+GRID_SIZES = (4, 8, 16, 32, 36, 40, 48, 64, 72, 128)
+MIXED_SIZES = tuple(p for p in GRID_SIZES if p & (p - 1))
+
+
+def lane_length(p, lane_max):
+    """Values per lane when a length-p transform is split over the fewest
+    lanes R (a power of two dividing p) that leave at most lane_max each."""
+    r = 1
+    while p // r > lane_max:
+        r *= 2
+    assert p % r == 0, (p, lane_max)
+    return p // r
+
+
 def codelet_specs():
     """(name, N, in_slots, out_slots, sign) for every codelet the kernels use.
 
@@ -443,10 +462,10 @@ def codelet_specs():
     # of length N = P / R: at most 32 values per lane in complex64, 16 in
     # complex128 (the kernels' rule).  When 2K+1 > N the orders fold and the
     # lane runs a full length-N transform.
-    for p in (4, 8, 16, 32, 64, 128):
+    for p in GRID_SIZES:
         k = (p - 1) // 4
         for lane_max in (64, 32, 16):
-            n = min(p, lane_max)
+            n = lane_length(p, lane_max)
             if 2 * k + 1 <= n:
                 pairs.add((n, k))
             else:
@@ -500,7 +519,9 @@ def main(path):
                 out.append(dispatch(fname, n, len(i), len(o), 'C', (len(o) - 1) // 2, family))
             else:
                 out.append(dispatch(fname, n, len(i), len(o), 'F', s, family))
-    for n in (8, 16, 32, 64, 128, 512):
+    # roots of unity: order 512 for the powers of two, order 720 (a multiple of
+    # every mixed size) for the others
+    for n in (8, 16, 32, 64, 128, 512, 720):
         out.append(twiddle_table(n))
     with open(path, 'w') as f:
         f.write('\n'.join(out))
@@ -515,10 +536,17 @@ def opcount_table():
     and every K <= (P - 1) / 4."""
     lines = ['// Generated by gen_fft.py: real operations of pruned length-P DFTs. Do not edit.',
              '#pragma once', '',
-             '// kPrunedOps[log2(P) - 2][K] = {expand (2K+1 -> P), crop (P -> 2K+1)}',
-             'static const int kPrunedOps[6][32][2] = {']
+             f'// kPrunedOps[pruned_ops_row(P)][K] = {{expand (2K+1 -> P), crop (P -> 2K+1)}},',
+             f'// P in {GRID_SIZES}',
+             f'static const int kPrunedGrid[{len(GRID_SIZES)}] = {{{", ".join(str(p) for p in GRID_SIZES)}}};',
+             'inline int pruned_ops_row(int P) {',
+             f'  for (int i = 0; i < {len(GRID_SIZES)}; ++i)',
+             '    if (kPrunedGrid[i] == P) return i;',
+             '  return -1;',
+             '}',
+             f'static const int kPrunedOps[{len(GRID_SIZES)}][32][2] = {{']
     rows = []
-    for p in (4, 8, 16, 32, 64, 128):
+    for p in GRID_SIZES:
         vals = []
         for k in range(32):
             if k <= (p - 1) // 4:

@@ -55,7 +55,9 @@ def test_strerror_and_defaults():
 
 
 @pytest.mark.parametrize("M,P", [((0, 0, 0), 4), ((1, 1, 1), 8), ((3, 3, 3), 16), ((3, 1, 0), 16),
-                                 ((7, 2, 2), 32), ((15, 15, 15), 64), ((16, 6, 6), 128),
+                                 ((7, 2, 2), 32), ((8, 2, 2), 36), ((1, 9, 0), 40), ((10, 10, 10), 48),
+                                 ((0, 0, 11), 48), ((12, 12, 12), 64), ((15, 15, 15), 64), ((16, 6, 6), 72),
+                                 ((17, 17, 17), 72), ((18, 0, 0), 128),
                                  ((31, 31, 31), 128), ((32, 0, 0), 256), ((63, 63, 63), 256),
                                  ((2, 64, 1), 512), ((127, 127, 127), 512)])
 def test_fft_size(M, P):
