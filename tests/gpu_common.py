@@ -69,3 +69,14 @@ def oracle_P(M):
             p += 1
         out.append(p)
     return tuple(out)
+
+
+def fp32_operator_tol(P):
+    """Bound on max|y - y_ref| / max|y_ref| for one complex64 application of
+    the operator on a grid of P points: each output passes six transforms of
+    log2 P butterfly levels (x, y, z, forward and inverse), and the rounding
+    of a level is at most the unit roundoff u32 = 2^-24 = 6.0e-8 relative to
+    the largest value; the contrast multiply and the Green epilogue add a
+    few u32 more.  6 log2(P) u32 + 4 u32: 2.4e-6 at P = 64, 2.8e-6 at 128."""
+    import math
+    return (6 * math.log2(P) + 4) * 6.0e-8

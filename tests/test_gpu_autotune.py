@@ -11,7 +11,7 @@ import itertools
 import numpy as np
 import pytest
 
-from gpu_common import k_vector, oracle_case, rel_err, say, seeded_field, to_torch
+from gpu_common import fp32_operator_tol, k_vector, oracle_case, rel_err, say, seeded_field, to_torch
 from oracle import gsm as O
 from paper_1501_01752_amd import inputs
 
@@ -53,7 +53,7 @@ def test_every_family_combination_applies_the_operator(tmp_path, precision, M):
     shape = (3, 2 * M + 1, 2 * M + 1, 2 * M + 1)
     dt = np.complex64 if precision == "c64" else np.complex128
     prec = gsm.GSM_MIXED if precision == "c64" else gsm.GSM_FP64
-    tol = 3e-6 if precision == "c64" else 1e-13
+    tol = fp32_operator_tol(P) if precision == "c64" else 1e-13
     x = seeded_field(shape, seed=5, dtype=dt)
     ref = None
     for fam in itertools.product((0, 1), repeat=4):
