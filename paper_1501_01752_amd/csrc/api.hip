@@ -431,7 +431,6 @@ struct Group {
   double2* part1 = nullptr;
   double* partn = nullptr;
   double* partc = nullptr;
-  int* any_reorth = nullptr;  // [restart+1] per-step second-pass flags
   long long* off = nullptr;   // [S] offsets of the systems in the caller's flat layout (complex values)
   void* exp = nullptr;        // [S] per-system results read back at the end
 };
@@ -575,7 +574,6 @@ size_t layout_group(Group& g, char* base, int restart, size_t vbytes, int nblk_c
   g.part1 = (double2*)take(S * g.shape.nchunk * (restart + 2) * sizeof(double2));
   g.partn = (double*)take(S * g.shape.nchunk * sizeof(double));
   g.partc = (double*)take(S * nblk_c * sizeof(double));
-  g.any_reorth = (int*)take((restart + 1) * sizeof(int));
   g.off = (long long*)take(S * sizeof(long long));
   g.exp = take(S * sizeof(SysExport));
   return off;
@@ -803,7 +801,6 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
   k.x64 = g.x64;
   k.r64 = g.r64;
   k.partc = g.partc;
-  k.any_reorth = g.any_reorth;
   return k;
 }
 
@@ -814,12 +811,11 @@ KrylovArgs<T> krylov_args(const Group& g, int restart) {
 // that launch).  Systems that finish a Krylov cycle early are only known at
 // the next host synchronisation, so step launches are attributed then.
 
-enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_FIN, K_CGS_RE, K_LSQ, K_CAST, K_FINAL,
+enum KClass { K_PASS_A, K_PASS_B, K_PASS_C, K_CGS_DOT, K_CGS_UPD, K_CGS_FIN, K_LSQ, K_CAST, K_FINAL,
               K_BICG_INIT, K_BICG_DOT, K_BICG_UPD, K_NBASE };
-const char* kClassNames[K_NBASE] = {"pass_a",          "pass_b",     "pass_c",  "cgs_dot",
-                                    "cgs_update",      "cgs_finish", "cgs_second_pass",
-                                    "lsq_update",      "cast_v0",    "resid_finalize",
-                                    "bicg_init",       "bicg_dot",   "bicg_update"};
+const char* kClassNames[K_NBASE] = {"pass_a",     "pass_b",     "pass_c",         "cgs_dot",
+                                    "cgs_update", "cgs_finish", "lsq_update",     "cast_v0",
+                                    "resid_finalize", "bicg_init", "bicg_dot", "bicg_update"};
 
 struct ProfRec {
   int cls;        // base class * 2 + (complex128 ? 1 : 0)
@@ -1125,6 +1121,7 @@ constexpr int kLead = GSM_LEAD;  // Arnoldi steps the host may run ahead of the 
 #endif
 constexpr int kChunk = GSM_CHUNK;  // Arnoldi steps per launch graph
 constexpr int kChunkLead = 2;      // graphs the host may run ahead of the device
+constexpr int kMaxLagSlots = 4;    // GMRES slots a cycle may add for systems running behind
 
 __global__ void k_export(const SysState* st, const double2* x64, GroupShape g, SysExport* out) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1221,6 +1218,9 @@ struct GroupRun {
     p.gate = GATE_INNER;
     pbi = p;                                // BiCGStab applies A (or A^H) itself
     pbi.mode = adjoint ? PC_ADJ : PC_FWD;
+    p.x = (cplx<T>*)g->V;                   // V_j -> V_j+1 at each system's step j
+    p.y = (cplx<T>*)g->V + n;
+    p.xstep = 1;
     V = (cplx<T>*)g->V;
     cap_outer = so->max_refine + 2;
     it_cap = std::max(1, so->max_iter / 2 + 1);
@@ -1298,18 +1298,16 @@ struct GroupRun {
                     [&] { return launch_bicg<T>(kt, BICG_XR, it, it_cap, st); }));
       HIP_TRY(timed(K_BICG_UPD, fp64, 0.0, it, 4 * vecb, st, [&] { return launch_bicg<T>(kt, BICG_P, it, it_cap, st); }));
     } else {
-      p.x = V + (long long)j * n;
-      p.y = V + (long long)(j + 1) * n;
-      const int rc = apply_passes<T>(p, r_pa | (j > 0 ? PA_NORMALIZE : 0), st, 0, j);
+      // the passes read V_j and write V_j+1 at each system's own step index
+      // (one behind the group's after a second Gram-Schmidt pass, which
+      // takes a step's slot; the passes skip a system in that slot)
+      const int rc = apply_passes<T>(p, r_pa, st, 0, j);
       if (rc) return rc;
-      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, j, st); }));
-      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, j, st); }));
-      // finish: Givens step, unless the first pass removed nearly all of w;
-      // those systems get a second Gram-Schmidt pass, whose kernels return
-      // at once when no system of the group asked for one (its bytes are
-      // not attributed: the host does not know how often it runs)
-      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, j, st); }));
-      HIP_TRY(timed(K_CGS_RE, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_second_pass<T>(kt, j, st); }));
+      HIP_TRY(timed(K_CGS_DOT, fp64, 0.0, j, (j + 2) * vecb, st, [&] { return launch_cgs_dot<T>(kt, st); }));
+      HIP_TRY(timed(K_CGS_UPD, fp64, 0.0, j, (j + 3) * vecb, st, [&] { return launch_cgs_update<T>(kt, st); }));
+      // finish: Givens step, unless the first pass removed nearly all of w:
+      // then the system's next slot makes the second pass
+      HIP_TRY(timed(K_CGS_FIN, fp64, 0.0, j, 0.0, st, [&] { return launch_cgs_finish<T>(kt, st); }));
     }
     ++j;
     return GSM_OK;
@@ -1425,6 +1423,19 @@ struct GroupRun {
         for (;;) {
           const int limit = bicg ? it_cap : m;
           if (j >= limit) {
+            // GMRES: slots past m for the systems seen to run behind after
+            // second Gram-Schmidt passes (pinned flag 1 + lag while running),
+            // so that they too complete m steps (with separate launches; a
+            // cycle issued as launch graphs ends at m)
+            if (!bicg && !graph && j < m + kMaxLagSlots) {
+              int lag = 0;
+              for (int s = 0; s < S; ++s) lag = std::max(lag, sl->h_inner[s] - 1);
+              if (j < m + lag) {
+                if ((rc = issue_step())) return rc;
+                *moved = true;
+                continue;
+              }
+            }
             *moved = true;
             return end_cycle();
           }

@@ -49,11 +49,10 @@ struct SysState {
   int iters;         // total Krylov iterations
   int refinements;   // FP64 residual evaluations
   int status;        // 0 running/converged, 1 not converged
-  int reorth;        // the current step needs a second Gram-Schmidt pass
-  int gs_count;      // blocks done with the current Gram-Schmidt update (last-block test)
-  int nreorth;       // second passes made (diagnostics)
-  int dot_count;     // blocks done with the current dot-product pass (last-block test)
-  int pad[2];
+  int reorth;        // step j awaits its second Gram-Schmidt pass (made in the next step's slot)
+  int nreorth;       // second passes requested (diagnostics)
+  int lag;           // second passes requested in the current cycle: slots the system runs behind
+  int pad[3];
   double rho;        // ||r|| of the last FP64 residual
   double rel;        // rho / bnorm
   double vscale;     // scale of the newest basis vector, applied as pass A reads it
@@ -120,7 +119,8 @@ struct PassArgs {
   hipEvent_t ev0, ev1;  // when set: stamped at the start and end of the launch
   int fam[4];           // codelet family per stage: pass A, pass B rows, pass B columns, pass C
   int xnorm;            // passes A and C read x scaled by the system's vscale
-  int pad;
+  int xstep;            // GMRES basis: x and y advance by the system's own step
+                        // (x = V_j, y = V_j+1 with j = st.j; x scaled when j > 0)
   cplx<T>* u;           // P >= 256: the plane pass's column-expanded planes [S][3][P][P][N1x]
   long long us;         // per-system stride of u (complex values)
 };
@@ -146,13 +146,12 @@ struct KrylovArgs {
   double2* x64;        // [S][n] FP64 iterate
   double2* r64;        // [S][n] FP64 residual
   double* partc;       // [S][nblk_c] pass C residual partials
-  int* host_inner;     // pinned host flags: cycle still running, per system (may be null)
-  int* any_reorth;     // [restart+1] per step: some system of the group needs a second pass
+  int* host_inner;     // pinned host flags, per system (may be null): 0 when the cycle has
+                       // ended for it, else 1 + the slots it runs behind (st.lag)
 };
-template <typename T> hipError_t launch_cgs_dot(const KrylovArgs<T>& a, int j, hipStream_t s);
-template <typename T> hipError_t launch_cgs_update(const KrylovArgs<T>& a, int j, hipStream_t s);
-template <typename T> hipError_t launch_cgs_finish(const KrylovArgs<T>& a, int j, hipStream_t s);
-template <typename T> hipError_t launch_cgs_second_pass(const KrylovArgs<T>& a, int j, hipStream_t s);
+template <typename T> hipError_t launch_cgs_dot(const KrylovArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_cgs_update(const KrylovArgs<T>& a, hipStream_t s);
+template <typename T> hipError_t launch_cgs_finish(const KrylovArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_lsq_update(const KrylovArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_cast_v0(const KrylovArgs<T>& a, hipStream_t s);
 // BiCGStab kernels (bicgstab.inc), selected by `kernel`; its vectors sit in

@@ -5,10 +5,9 @@
 
 namespace gsm {
 #define GSM_KRYLOV_INST(T)                                                                  \
-  template hipError_t launch_cgs_dot<T>(const KrylovArgs<T>&, int, hipStream_t);           \
-  template hipError_t launch_cgs_update<T>(const KrylovArgs<T>&, int, hipStream_t);        \
-  template hipError_t launch_cgs_finish<T>(const KrylovArgs<T>&, int, hipStream_t);        \
-  template hipError_t launch_cgs_second_pass<T>(const KrylovArgs<T>&, int, hipStream_t);   \
+  template hipError_t launch_cgs_dot<T>(const KrylovArgs<T>&, hipStream_t);                \
+  template hipError_t launch_cgs_update<T>(const KrylovArgs<T>&, hipStream_t);             \
+  template hipError_t launch_cgs_finish<T>(const KrylovArgs<T>&, hipStream_t);             \
   template hipError_t launch_lsq_update<T>(const KrylovArgs<T>&, hipStream_t);             \
   template hipError_t launch_cast_v0<T>(const KrylovArgs<T>&, hipStream_t);                 \
   template hipError_t launch_bicg<T>(const KrylovArgs<T>&, int, int, int, hipStream_t);
