@@ -79,13 +79,24 @@ enum { GSM_MIXED = 0, GSM_FP64 = 1 };
 enum { GSM_GMRES = 0, GSM_BICGSTAB = 1 };
 /* gsm_solver_opts.flags */
 enum {
-  GSM_OUT_HOST = 1,   /* E_out / eps_eff / grad are host pointers */
-  GSM_SOLVE_GRAPH = 2 /* issue GMRES steps as captured launch graphs (see below) */
+  GSM_OUT_HOST = 1,    /* E_out / eps_eff / grad are host pointers */
+  GSM_SOLVE_GRAPH = 2, /* issue GMRES steps as captured launch graphs (see below) */
+  GSM_SOLVE_REORTH = 4 /* GMRES: a second Gram-Schmidt pass at every Arnoldi step
+                          (classical Gram-Schmidt twice) instead of only where the
+                          first pass removed nearly all of the new vector; see below */
 };
+/* Second Gram-Schmidt passes.  A system whose step needs a second pass makes
+ * it in the slot of its next step (the other systems of its launch group go
+ * on), so it runs one slot behind; the host adds up to four slots past the
+ * restart length for the systems it has seen fall behind.  With
+ * GSM_SOLVE_REORTH every step takes two slots, so a cycle completes about
+ * (restart + 4) / 2 steps: a reference mode (tests, badly conditioned
+ * systems), not a fast one.  info.reorth counts the second passes. */
 /* Launch graphs.  With GSM_SOLVE_GRAPH (and launch profiling off) the
  * Arnoldi steps of a GMRES cycle are issued as captured HIP graphs of four
- * steps each (one graph launch instead of about nine kernel launches per
- * step).  A plan keeps the instantiated graphs of its recent groups and
+ * steps each (one graph launch instead of six kernel launches per step; a
+ * cycle issued so ends after the restart length, without slots added for
+ * systems running behind).  A plan keeps the instantiated graphs of its recent groups and
  * reuses one when a later call would issue exactly the same launches (same
  * kernel arguments: same plan, workspace address, group composition and
  * options), so repeated solves of one batch pay the capture once.  Results
@@ -156,7 +167,7 @@ typedef struct gsm_solver_opts {
   int32_t max_refine; /* cap on FP64 residual evaluations per system; default 200 */
   int32_t precision;  /* GSM_MIXED (complex64 Krylov inside FP64 refinement) or GSM_FP64 */
   int32_t method;     /* GSM_GMRES or GSM_BICGSTAB */
-  int32_t flags;      /* GSM_OUT_HOST */
+  int32_t flags;      /* GSM_OUT_HOST | GSM_SOLVE_GRAPH | GSM_SOLVE_REORTH */
   const double* x0;   /* NULL or an initial guess (device, layout of E_out) */
   int32_t group_max;  /* systems per launch group, >= 0 (0: no limit); default 32.
                          The systems of a call that share (M, P) are split into
@@ -174,7 +185,7 @@ typedef struct gsm_solve_info {
   int32_t iterations;  /* Krylov iterations (matrix-vector products in the Krylov precision) */
   int32_t refinements; /* FP64 residual evaluations */
   int32_t fft_size;    /* P, the FFT grid per axis */
-  int32_t reorth;      /* Arnoldi steps that needed a second Gram-Schmidt pass */
+  int32_t reorth;      /* Arnoldi steps that asked for a second Gram-Schmidt pass */
   int32_t reserved;
   double rel_residual; /* final ||b - A x||_2 / ||b||_2 evaluated in FP64 */
   double eps_b;        /* basis permittivity used */

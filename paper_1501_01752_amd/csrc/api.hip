@@ -294,7 +294,7 @@ int check_solver_opts(const gsm_solver_opts* s) {
   if (s->method != GSM_GMRES && s->method != GSM_BICGSTAB) return fail(GSM_E_ARG, "unknown method %d", s->method);
   if (s->method == GSM_BICGSTAB && s->restart < 5)
     return fail(GSM_E_ARG, "BiCGStab keeps six vectors per system: restart must be >= 5");
-  if (s->flags & ~(GSM_OUT_HOST | GSM_SOLVE_GRAPH)) return fail(GSM_E_ARG, "unknown solver flags");
+  if (s->flags & ~(GSM_OUT_HOST | GSM_SOLVE_GRAPH | GSM_SOLVE_REORTH)) return fail(GSM_E_ARG, "unknown solver flags");
   if (s->group_max < 0) return fail(GSM_E_ARG, "group_max must be >= 0");
   if (s->formulation != GSM_FORM_E && s->formulation != GSM_FORM_H)
     return fail(GSM_E_ARG, "unknown formulation %d", s->formulation);
@@ -1195,6 +1195,7 @@ struct GroupRun {
     k64 = krylov_args<double>(*g, m);
     kt = krylov_args<T>(*g, m);
     kt.host_inner = sl->h_inner;
+    kt.reorth_all = (so->flags & GSM_SOLVE_REORTH) ? 1 : 0;
     r = pass_args<double>(*g, grid);
     r.g.nblk_c = nblk_c_for(g->shape, true);
     k64.g.nblk_c = r.g.nblk_c;

@@ -140,7 +140,8 @@ struct KrylovArgs {
   SysState* st;
   cplx<T>* V;          // basis [S][restart+1][n]
   int restart;
-  int unused;          // zero: no padding bytes (the bytes of the arguments key cached launch graphs)
+  int reorth_all;      // second Gram-Schmidt pass at every step (GSM_SOLVE_REORTH); the int
+                       // also keeps the struct free of padding bytes (its bytes key cached launch graphs)
   double2* part1;      // [S][nchunk][restart+2] Gram-Schmidt partial sums
   double* partn;       // [S][nchunk]
   double2* x64;        // [S][n] FP64 iterate

@@ -18,7 +18,7 @@ GSM_E_ARG, GSM_E_NONFINITE, GSM_E_NOMEM, GSM_E_DEVICE = -1, -2, -3, -4
 GSM_E_SINGULAR, GSM_E_WORKSPACE, GSM_E_UNSUPPORTED = -5, -6, -7
 GSM_MIXED, GSM_FP64 = 0, 1
 GSM_GMRES, GSM_BICGSTAB = 0, 1
-GSM_OUT_HOST, GSM_SOLVE_GRAPH = 1, 2
+GSM_OUT_HOST, GSM_SOLVE_GRAPH, GSM_SOLVE_REORTH = 1, 2, 4
 GSM_APPLY_FORWARD, GSM_APPLY_ADJOINT, GSM_APPLY_FORWARD_H = 0, 1, 2
 GSM_FORM_E, GSM_FORM_H = 0, 1
 GSM_PLAN_AUTOTUNE = 1

@@ -178,3 +178,41 @@ def test_second_gram_schmidt_pass(precision):
         ref = O.solve_dense(c, M, q, 2.0, [np.array(a, complex)]).ravel()
         assert rel_err(E[off:off + ref.size], ref) <= 1e-10
         off += ref.size
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_second_pass_at_every_step(precision, graph):
+    """GSM_SOLVE_REORTH: every Arnoldi step asks for the second Gram-Schmidt
+    pass, which each system makes in the slot of its next step, so in one
+    launch group systems that converge after different numbers of steps run
+    at different step indices, and the host adds slots past the restart
+    length for them (separate launches only).  Every field must equal the
+    dense LU solution, and every completed step must have asked for a pass."""
+    gsm = G()
+    w = inputs.sphere_lattice_small()
+    M = w["M"]
+    lam = w["wavelength"]
+    plan = gsm.Plan(w["eps"], w["period"], M)
+    dirs = [(0.0, 0.0, 1.0), (0.3, -0.2, 1.0), (-0.5, 0.4, 0.6)]
+    drives = [(1.0, 0.0, 0.0), (0.2, 1.0, 0.3j)]
+    insts = []
+    for d in dirs:
+        inst = gsm.make_instance(lam, k_vector(lam, d), M, drives)
+        inst.eps_b = plan.basis_eps(inst)
+        insts.append(inst)
+    prec = gsm.GSM_FP64 if precision == "fp64" else gsm.GSM_MIXED
+    flags = gsm.GSM_SOLVE_REORTH | (gsm.GSM_SOLVE_GRAPH if graph else 0)
+    say(f"second pass at every step, {precision}, graph={graph}")
+    E, info, st = plan.solve(insts, gsm.default_opts(tol=1e-11, precision=prec, restart=12, flags=flags))
+    assert st == gsm.GSM_OK
+    assert all(i["reorth"] >= i["iterations"] > 0 for i in info), info
+    E = E.cpu().numpy()
+    off = 0
+    for d, inst in zip(dirs, insts):
+        k = k_vector(lam, d)
+        c, q = oracle_case(w["eps"], w["period"], lam, k, M)
+        ref = O.solve_dense(c, M, q, inst.eps_b, [np.array(a, complex) for a in drives]).ravel()
+        assert rel_err(E[off:off + ref.size], ref) <= 1e-9
+        off += ref.size
+    plan.close()
