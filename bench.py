@@ -18,8 +18,8 @@ the dominant kernel class (found in one extra profiled step before the timed
 ones): its algorithmic bytes or flops over the durations of its launches in
 the timed steps, one launch in four bracketed by a hipEvent pair on its own
 stream (only that class carries events there); the per-class table of the
-extra step; the
-plain FP64 GPU solve of the same workload; the literal 4-solve case, the
+extra step; the whole step against HBM (the algorithmic bytes of all its
+launches over its wall time); the plain FP64 GPU solve of the same workload; the literal 4-solve case, the
 uneven 256-instance sweep, the 32^3-voxel inverse-design gradient and the
 M = 31 woodpile batch as further lines of the same JSON object; Table 1's
 single-solve workload at three sizes (context beside the paper's times); the
@@ -633,6 +633,7 @@ def main():
     prof_all = gsm.profile_end()
     kernels = kernel_table(prof_all)
     matvec = matvec_hbm(prof_all)
+    step_bytes = sum(v["bytes"] for v in prof_all.values())
     dom_name = next(iter(kernels))
     dom_class = dom_name.rsplit("_", 1)[0]
 
@@ -653,6 +654,14 @@ def main():
     krylov = {k: round(STATS[k] / max(1, STATS["solves"]), 2) for k in ("iterations", "refinements", "reorth")}
     dt = t1 - t0
     value = total / dt
+    # the whole solve against HBM: the algorithmic bytes of every launch of
+    # one step (passes, Gram-Schmidt, least squares, FP64 residuals, each by
+    # its definition) over the timed steps' wall time per step
+    step_gbs = step_bytes / (dt / args.steps) / 1e9
+    step_hbm = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(step_gbs / HBM_PEAK_GBS, 4), "bytes_per_step": int(step_bytes),
+                "bytes": "algorithmic bytes of every launch of one step, counted on an extra step with every "
+                         "launch timed, over the wall time of a timed step"}
     # roofline of the dominant class from its launches in the timed steps
     roofline = roofline_of(dom_name, prof[dom_name])
     roofline["group_max"] = opts.group_max
@@ -760,6 +769,7 @@ def main():
         "roofline": roofline,
         "roofline_one_group": one_group,
         "matvec_hbm": matvec,
+        "step_hbm": step_hbm,
         "copy_bandwidth": copy_bw,
         "fp64_gpu_solve": fp64,
         "as_configured": as_configured,
