@@ -191,8 +191,8 @@ def uneven_sweep(gsm, inputs, steps, autotune):
         inst.eps_b = plan.basis_eps(inst)
         insts.append(inst)
     opts = gsm.default_opts(tol=TOL, precision=gsm.GSM_MIXED, restart=30)
-    # two untimed calls (the first tunes and builds the grids; on a freshly
-    # started host the second still ran up to twice as long as the later ones)
+    # two untimed calls (the first tunes the codelet families and builds the
+    # grids), then the timed ones
     for _ in range(2):
         plan.solve(insts, opts)
     torch.cuda.synchronize()
