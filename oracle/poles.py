@@ -96,10 +96,16 @@ def pole_search(kappa, xi, n_poles, n_div):
 
 
 def dominant_pole(eta, zeta, kappa_min, kappa_max):
-    """The pole with real part inside [kappa_min, kappa_max] of largest |zeta|
-    (index into eta), or -1 if none lies inside."""
+    """The pole of largest |zeta| among those with real part inside
+    [kappa_min, kappa_max] and imaginary part at most half the window's
+    width (index into eta), or -1 if there is none.  The modes of a lossless
+    medium are real poles; poles far off the real axis only model the
+    regular part of xi (the paper takes N_p above the two modes of a
+    direction for that reason), and under rounding-level changes of the
+    samples such a pole can wander into the window with a large amplitude."""
     best, idx = -1.0, -1
+    half = 0.5 * (kappa_max - kappa_min)
     for j, (e, z) in enumerate(zip(eta, zeta)):
-        if kappa_min <= e.real <= kappa_max and abs(z) > best:
+        if kappa_min <= e.real <= kappa_max and abs(e.imag) <= half and abs(z) > best:
             best, idx = abs(z), j
     return idx
