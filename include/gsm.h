@@ -436,8 +436,11 @@ typedef struct gsm_pole_result {
   int32_t status;            /* worst status of the mesh solves; GSM_E_SINGULAR if Eq.(9)
                                 or the eigenvalue iteration failed */
   int32_t n_poles;
-  int32_t best;              /* index of the pole with real part in [kappa_min, kappa_max]
-                                and the largest |zeta|; -1 if none */
+  int32_t best;              /* index of the pole of largest |zeta| among those with real
+                                part in [kappa_min, kappa_max] and |imaginary part| at most
+                                (kappa_max - kappa_min) / 2 (the modes of a lossless medium
+                                are real; poles far off the axis model the regular part of
+                                xi); -1 if none */
   int32_t iterations;        /* Krylov iterations summed over the mesh */
   double eta[GSM_POLE_MAX_NP][2];   /* poles (re, im), ascending real part */
   double zeta[GSM_POLE_MAX_NP][2];  /* amplitudes */
@@ -464,6 +467,39 @@ int gsm_pole_search(gsm_plan_t plan, int32_t n_q, const gsm_pole_query* q,
  * (no synchronisation). */
 int gsm_pole_fit(int32_t n, int32_t n_poles, int32_t n_div, const double* kappa, const double* xi,
                  double* eta, double* zeta, int32_t* status, void* stream);
+
+/* ------------------------------------------------ Fresnel normal surface
+ * The paper reads the effective tensor off the propagation constants: a
+ * direction of the effective medium carries two refractive indices, the
+ * roots of the Fresnel normal equation ("Modes in 3D crystals"; in its
+ * uniaxial and biaxial examples the principal axes are the lattice axes).
+ * A plane wave of unit normal k and index n in a medium of real symmetric
+ * permittivity eps obeys (eps - n^2 (I - k k^T)) E = 0, whose determinant is
+ * the quadratic (k^T eps k) n^4 - (tr C - k^T C k) n^2 + det(eps), C the
+ * adjugate of eps.  Host functions: no device work, any thread. */
+
+/* The two indices of direction k_hat (nonzero, need not be normalised) for
+ * eps [3][3] row-major (symmetric; the upper triangle is read), ascending,
+ * into n_out[2].  GSM_E_ARG for NULL pointers or a zero direction,
+ * GSM_E_NONFINITE for NaN/Inf, GSM_E_SINGULAR when the roots are not both
+ * real and positive (eps not positive definite across k). */
+int gsm_fresnel_indices(const double* eps, const double* k_hat, double* n_out);
+
+/* Real symmetric tensor whose normal surface passes closest to n_dir
+ * observed directions k_hat [n_dir][3] with their two indices each,
+ * n_pair [n_dir][2] (either order).  diagonal != 0: principal axes along
+ * x, y, z, three values (n_dir >= 3); else all six components (n_dir >= 6).
+ * Method: the product of a direction's two roots n1^2 n2^2 is
+ * det(eps) / (k^T eps k), linear in eps / det(eps), which gives a linear
+ * least-squares estimate; Levenberg-Marquardt steps on the residuals
+ * det(eps - n^2 (I - k k^T)) / n^6 (analytic Jacobian from the adjugate)
+ * refine it.  eps_out [3][3] row-major; rms_out (may be NULL) the root mean
+ * square of those residuals.  GSM_E_ARG for NULL pointers, too few
+ * directions, a zero direction or a non-positive index; GSM_E_NONFINITE for
+ * NaN/Inf; GSM_E_SINGULAR when the directions do not determine the tensor
+ * or the estimate is not positive definite. */
+int gsm_fresnel_fit(int32_t n_dir, const double* k_hat, const double* n_pair, int32_t diagonal, double* eps_out,
+                    double* rms_out);
 
 /* Launch graphs of a plan so far: *captured = graphs captured and
  * instantiated, *launched = graph launches (each runs a few Krylov steps of

@@ -2535,7 +2535,11 @@ int gsm_pole_search(gsm_plan_t p, int32_t n_q, const gsm_pole_query* q, const gs
         r.zeta[k][c] = zeta[2 * (et + k) + c];
       }
       const double az = std::hypot(r.zeta[k][0], r.zeta[k][1]);
-      if (fst[i] == GSM_OK && r.eta[k][0] >= q[i].kappa_min && r.eta[k][0] <= q[i].kappa_max && az > bz) {
+      // a mode of the window: real part inside it, within half its width of
+      // the real axis (poles far off it model the regular part of xi)
+      const bool near = r.eta[k][0] >= q[i].kappa_min && r.eta[k][0] <= q[i].kappa_max &&
+                        std::fabs(r.eta[k][1]) <= 0.5 * (q[i].kappa_max - q[i].kappa_min);
+      if (fst[i] == GSM_OK && near && az > bz) {
         bz = az;
         r.best = k;
       }
@@ -2567,6 +2571,222 @@ int gsm_pole_fit(int32_t n, int32_t n_poles, int32_t n_div, const double* kappa,
   fa.zeta = zeta;
   fa.status = status;
   HIP_TRY(launch_pole_fit(fa, (hipStream_t)stream));
+  return GSM_OK;
+}
+
+namespace {
+
+// ---- Fresnel normal surface (host): 3x3 row-major helpers
+
+double det3(const double* a) {
+  return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+         a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+// adjugate: adj(a) a = det(a) I; d det(a) / d a_ij = adj(a)_ji
+void adj3(const double* a, double* c) {
+  c[0] = a[4] * a[8] - a[5] * a[7];
+  c[1] = a[2] * a[7] - a[1] * a[8];
+  c[2] = a[1] * a[5] - a[2] * a[4];
+  c[3] = a[5] * a[6] - a[3] * a[8];
+  c[4] = a[0] * a[8] - a[2] * a[6];
+  c[5] = a[2] * a[3] - a[0] * a[5];
+  c[6] = a[3] * a[7] - a[4] * a[6];
+  c[7] = a[1] * a[6] - a[0] * a[7];
+  c[8] = a[0] * a[4] - a[1] * a[3];
+}
+
+bool unit3(const double* k, double* u) {
+  const double nn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+  if (!(nn > 0.0)) return false;
+  for (int i = 0; i < 3; ++i) u[i] = k[i] / nn;
+  return true;
+}
+
+// roots t = n^2, ascending, of (u.e.u) t^2 - (tr C - u.C.u) t + det e = 0
+int fresnel_roots(const double* e, const double* u, double* t) {
+  double c[9];
+  adj3(e, c);
+  double qa = 0.0, qc = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      qa += u[i] * e[3 * i + j] * u[j];
+      qc += u[i] * c[3 * i + j] * u[j];
+    }
+  const double b = c[0] + c[4] + c[8] - qc, d = det3(e);
+  if (!(qa > 0.0) || !(d > 0.0)) return GSM_E_SINGULAR;
+  double disc = b * b - 4.0 * qa * d;
+  if (disc < 0.0) {
+    if (disc < -1e-12 * b * b) return GSM_E_SINGULAR;
+    disc = 0.0;  // a double root (isotropic, or an optic axis) rounded below zero
+  }
+  const double q = 0.5 * (b + std::sqrt(disc));
+  if (!(q > 0.0)) return GSM_E_SINGULAR;
+  const double t1 = d / q, t2 = q / qa;  // smaller, larger (product d / qa)
+  t[0] = std::min(t1, t2);
+  t[1] = std::max(t1, t2);
+  return GSM_OK;
+}
+
+// symmetric tensor of the fit parameters: xx, yy, zz (diagonal), then xy, xz, yz
+void fresnel_tensor(const double* p, bool diag, double* e) {
+  e[0] = p[0];
+  e[4] = p[1];
+  e[8] = p[2];
+  e[1] = e[3] = diag ? 0.0 : p[3];
+  e[2] = e[6] = diag ? 0.0 : p[4];
+  e[5] = e[7] = diag ? 0.0 : p[5];
+}
+
+// Solve the np x np symmetric positive system A x = b in place (Cholesky);
+// false when a pivot falls below rel_tol times the largest diagonal.
+bool spd_solve(double* A, double* b, int np, double rel_tol) {
+  double dmax = 0.0;
+  for (int i = 0; i < np; ++i) dmax = std::max(dmax, A[i * np + i]);
+  if (!(dmax > 0.0)) return false;
+  for (int j = 0; j < np; ++j) {
+    double s = A[j * np + j];
+    for (int k = 0; k < j; ++k) s -= A[j * np + k] * A[j * np + k];
+    if (!(s > rel_tol * dmax)) return false;
+    const double l = std::sqrt(s);
+    A[j * np + j] = l;
+    for (int i = j + 1; i < np; ++i) {
+      double v = A[i * np + j];
+      for (int k = 0; k < j; ++k) v -= A[i * np + k] * A[j * np + k];
+      A[i * np + j] = v / l;
+    }
+  }
+  for (int i = 0; i < np; ++i) {
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= A[i * np + k] * b[k];
+    b[i] = v / A[i * np + i];
+  }
+  for (int i = np - 1; i >= 0; --i) {
+    double v = b[i];
+    for (int k = i + 1; k < np; ++k) v -= A[k * np + i] * b[k];
+    b[i] = v / A[i * np + i];
+  }
+  return true;
+}
+
+}  // namespace
+
+int gsm_fresnel_indices(const double* eps, const double* k_hat, double* n_out) {
+  if (!eps || !k_hat || !n_out) return fail(GSM_E_ARG, "NULL argument");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(eps[i])) return fail(GSM_E_NONFINITE, "eps not finite");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(k_hat[i])) return fail(GSM_E_NONFINITE, "k_hat not finite");
+  double u[3], e[9], t[2];
+  if (!unit3(k_hat, u)) return fail(GSM_E_ARG, "zero direction");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) e[3 * i + j] = eps[3 * std::min(i, j) + std::max(i, j)];
+  if (fresnel_roots(e, u, t) != GSM_OK)
+    return fail(GSM_E_SINGULAR, "the normal equation has no two positive roots along this direction");
+  n_out[0] = std::sqrt(t[0]);
+  n_out[1] = std::sqrt(t[1]);
+  return GSM_OK;
+}
+
+int gsm_fresnel_fit(int32_t n_dir, const double* k_hat, const double* n_pair, int32_t diagonal, double* eps_out,
+                    double* rms_out) {
+  if (!k_hat || !n_pair || !eps_out) return fail(GSM_E_ARG, "NULL argument");
+  const bool diag = diagonal != 0;
+  const int np = diag ? 3 : 6;
+  if (n_dir < np) return fail(GSM_E_ARG, "%d directions cannot determine %d components", n_dir, np);
+  std::vector<double> U(3 * (size_t)n_dir), T(2 * (size_t)n_dir);
+  for (int d = 0; d < n_dir; ++d) {
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(k_hat[3 * d + i])) return fail(GSM_E_NONFINITE, "direction %d not finite", d);
+    if (!unit3(k_hat + 3 * d, &U[3 * d])) return fail(GSM_E_ARG, "direction %d is zero", d);
+    for (int r = 0; r < 2; ++r) {
+      const double n = n_pair[2 * d + r];
+      if (!std::isfinite(n)) return fail(GSM_E_NONFINITE, "index %d of direction %d not finite", r, d);
+      if (!(n > 0.0)) return fail(GSM_E_ARG, "index %d of direction %d is not positive", r, d);
+      T[2 * d + r] = n * n;
+    }
+  }
+  // linear estimate: u.E.u = 1 / (t1 t2) with E = eps / det(eps)
+  double N[36] = {}, g[6] = {};
+  for (int d = 0; d < n_dir; ++d) {
+    const double* u = &U[3 * d];
+    const double row[6] = {u[0] * u[0], u[1] * u[1], u[2] * u[2], 2 * u[0] * u[1], 2 * u[0] * u[2], 2 * u[1] * u[2]};
+    const double b = 1.0 / (T[2 * d] * T[2 * d + 1]);
+    for (int i = 0; i < np; ++i) {
+      g[i] += row[i] * b;
+      for (int j = 0; j < np; ++j) N[i * np + j] += row[i] * row[j];
+    }
+  }
+  if (!spd_solve(N, g, np, 1e-12)) return fail(GSM_E_SINGULAR, "the directions do not determine the tensor");
+  double e[9], p[6];
+  fresnel_tensor(g, diag, e);
+  const double dE = det3(e);
+  if (!(dE > 0.0)) return fail(GSM_E_SINGULAR, "the linear estimate is not positive definite");
+  const double scale = 1.0 / std::sqrt(dE);
+  for (int i = 0; i < np; ++i) p[i] = g[i] * scale;
+  // Levenberg-Marquardt on r = det(eps - t P) / t^3
+  const int m = 2 * n_dir;
+  std::vector<double> r(m), rt(m), J((size_t)m * np);
+  // residuals of parameters pp into rr (and the Jacobian into J when asked)
+  auto eval = [&](const double* pp, double* rr, bool jac) {
+    double ee[9], A[9], C[9], ss = 0.0;
+    fresnel_tensor(pp, diag, ee);
+    for (int o = 0; o < m; ++o) {
+      const double* u = &U[3 * (o / 2)];
+      const double t = T[o], it3 = 1.0 / (t * t * t);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) A[3 * i + j] = ee[3 * i + j] - t * ((i == j ? 1.0 : 0.0) - u[i] * u[j]);
+      rr[o] = det3(A) * it3;
+      ss += rr[o] * rr[o];
+      if (jac) {
+        adj3(A, C);
+        double* Jo = &J[(size_t)o * np];
+        Jo[0] = C[0] * it3;
+        Jo[1] = C[4] * it3;
+        Jo[2] = C[8] * it3;
+        if (!diag) {
+          Jo[3] = (C[1] + C[3]) * it3;
+          Jo[4] = (C[2] + C[6]) * it3;
+          Jo[5] = (C[5] + C[7]) * it3;
+        }
+      }
+    }
+    return ss;
+  };
+  double ss = eval(p, r.data(), true), mu = 1e-3;
+  for (int it = 0; it < 200 && ss > 0.0; ++it) {
+    double JtJ[36] = {}, Jtr[6] = {};
+    for (int o = 0; o < m; ++o)
+      for (int i = 0; i < np; ++i) {
+        Jtr[i] -= J[(size_t)o * np + i] * r[o];
+        for (int j = 0; j < np; ++j) JtJ[i * np + j] += J[(size_t)o * np + i] * J[(size_t)o * np + j];
+      }
+    double A[36], step[6], trial[6];
+    for (int i = 0; i < np * np; ++i) A[i] = JtJ[i];
+    for (int i = 0; i < np; ++i) {
+      A[i * np + i] *= 1.0 + mu;
+      step[i] = Jtr[i];
+    }
+    if (!spd_solve(A, step, np, 1e-300)) break;
+    double sn = 0.0, pn = 0.0;
+    for (int i = 0; i < np; ++i) {
+      trial[i] = p[i] + step[i];
+      sn += step[i] * step[i];
+      pn += p[i] * p[i];
+    }
+    const double ss_new = eval(trial, rt.data(), false);
+    if (ss_new < ss) {
+      for (int i = 0; i < np; ++i) p[i] = trial[i];
+      ss = eval(p, r.data(), true);
+      mu = std::max(mu / 3.0, 1e-12);
+    } else {
+      mu *= 4.0;
+      if (mu > 1e12) break;
+    }
+    if (sn <= 1e-30 * (1.0 + pn)) break;
+  }
+  fresnel_tensor(p, diag, eps_out);
+  if (rms_out) *rms_out = std::sqrt(eval(p, rt.data(), false) / m);
   return GSM_OK;
 }
 

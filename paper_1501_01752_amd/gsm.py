@@ -120,6 +120,31 @@ def pole_fit(kappa, xi, n_poles, n_div, stream=None):
     return eta, zeta, status
 
 
+def fresnel_indices(eps, k_hat):
+    """The two refractive indices (ascending) of direction k_hat in a medium
+    of real symmetric permittivity eps (gsm_fresnel_indices, host)."""
+    e = (C.c_double * 9)(*np.asarray(eps, dtype=np.float64).reshape(9))
+    k = (C.c_double * 3)(*np.asarray(k_hat, dtype=np.float64).reshape(3))
+    out = (C.c_double * 2)()
+    _check(lib().gsm_fresnel_indices(e, k, out))
+    return np.array([out[0], out[1]])
+
+
+def fresnel_fit(k_hats, n_pairs, diagonal=False):
+    """(eps 3x3, rms) fitted to directions and their two indices each
+    (gsm_fresnel_fit, host); diagonal: principal axes along x, y, z."""
+    k = np.ascontiguousarray(k_hats, dtype=np.float64).reshape(-1, 3)
+    n = np.ascontiguousarray(n_pairs, dtype=np.float64).reshape(-1, 2)
+    if k.shape[0] != n.shape[0]:
+        raise ValueError("one pair of indices per direction")
+    out = (C.c_double * 9)()
+    rms = C.c_double()
+    _check(lib().gsm_fresnel_fit(k.shape[0], k.ctypes.data_as(C.POINTER(C.c_double)),
+                                 n.ctypes.data_as(C.POINTER(C.c_double)), 1 if diagonal else 0, out,
+                                 C.byref(rms)))
+    return np.array(out[:]).reshape(3, 3), rms.value
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("refinements", C.c_int32),
                 ("fft_size", C.c_int32), ("reorth", C.c_int32), ("reserved", C.c_int32),
@@ -186,6 +211,9 @@ _SIGS = {
                                   C.c_void_p, C.c_size_t, C.POINTER(PoleResult), C.c_void_p]),
     "gsm_pole_fit": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gsm_fresnel_indices": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gsm_fresnel_fit": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int32,
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gsm_profile_begin": (C.c_int, []),
     "gsm_profile_begin_only": (C.c_int, [C.c_char_p]),
     "gsm_profile_begin_sampled": (C.c_int, [C.c_char_p, C.c_int32]),
@@ -504,6 +532,36 @@ class Plan:
                                    ws.numel(), out, _stream(stream))
         _check(st)
         return [r.as_dict() for r in out], st
+
+    def fresnel_tensor(self, wavelength, M, n_lo, n_hi, opts=None, n_poles=5, n_div=10, eps_b=0.0,
+                       stream=None):
+        """The effective tensor from propagation constants, for lattices
+        whose principal axes are the lattice axes: pole searches along x, y
+        and z with the two transverse drives each (xi = the driven component
+        of the zeroth order; one call), the indices of the dominant poles
+        with n in [n_lo, n_hi], and the diagonal tensor fitted to the three
+        index pairs (gsm_fresnel_fit).  Each principal index is measured
+        along two directions; the fit's rms shows how far they differ
+        (spatial dispersion at a finite period).  Returns (eps 3x3, rms,
+        index pairs [3][2] (along x, y, z; the two drives in axis order),
+        the six pole-search results)."""
+        k0 = 2 * np.pi / wavelength
+        queries = []
+        for ax in range(3):
+            for other in (a for a in range(3) if a != ax):
+                k_hat = [0.0, 0.0, 0.0]
+                k_hat[ax] = 1.0
+                drive = [0.0, 0.0, 0.0]
+                drive[other] = 1.0
+                queries.append(make_pole_query(wavelength, k_hat, M, n_lo * k0, n_hi * k0, drive=drive,
+                                               component=other, n_poles=n_poles, n_div=n_div, eps_b=eps_b))
+        res, st = self.pole_search(queries, opts, stream)
+        missing = [i for i, r in enumerate(res) if r["best"] < 0]
+        if missing:
+            raise GsmError(GSM_E_SINGULAR, f"no pole with n in [{n_lo}, {n_hi}] for queries {missing}")
+        pairs = np.array([[res[2 * ax]["n_eff"], res[2 * ax + 1]["n_eff"]] for ax in range(3)])
+        eps, rms = fresnel_fit(np.eye(3), pairs, diagonal=True)
+        return eps, rms, pairs, res
 
     def solve_adjoint(self, insts, rhs, opts=None, stream=None):
         """lambda = A^-H rhs for every (instance, drive); rhs complex128 (device)."""
