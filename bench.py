@@ -25,8 +25,9 @@ M = 31 woodpile batch as further lines of the same JSON object; Table 1's
 single-solve workload at three sizes (context beside the paper's times); the
 achievable copy bandwidth; the pole search of Eqs.(6)-(10) on the paper's
 Fig. 2 lattices (E and H systems, beside the printed indices); the headline
-batch through the H-field system of Eq.(5); and the CPU oracle (scipy.fft
-on the host threads + SciPy GMRES, FP64) timed on a bounded sample.
+batch through the H-field system of Eq.(5); the Fresnel-tensor retrieval on
+Fig. 4's uniaxial lattices; and the CPU oracle (scipy.fft on the host
+threads + SciPy GMRES, FP64) timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -76,6 +77,8 @@ def parse():
                          "(default: --steps; 0: skip)")
     ap.add_argument("--pole-steps", type=int, default=2,
                     help="timed rounds of the Fig. 2 pole searches (E and H systems, 0: skip)")
+    ap.add_argument("--fresnel-steps", type=int, default=2,
+                    help="timed rounds of the Fig. 4 Fresnel-tensor retrievals (0: skip)")
     ap.add_argument("--hfield-steps", type=int, default=2,
                     help="timed steps of the headline batch through the H-field system (0: skip)")
     ap.add_argument("--table1-reps", type=int, default=10,
@@ -207,8 +210,10 @@ def uneven_sweep(gsm, inputs, steps, autotune):
     gsm.profile_begin()
     plan.solve(insts, opts)
     prof = gsm.profile_end()
+    families = {int(m): plan.tuning((int(m),) * 3)[0] for m in sorted(set(Ms.tolist()))}
     return {"value": round(len(insts) / dt, 3), "unit": "solves/s", "instances": len(insts),
             "order_counts": [int(Ms.min()), int(Ms.max())], "ms_per_step": round(dt * 1e3, 3),
+            "codelet_families": families,
             "max_rel_residual": max(i["rel_residual"] for i in info),
             "fft_sizes": sorted({int(i["fft_size"]) for i in info}),
             "roofline": matvec_hbm(prof), "roofline_fp64_residual": matvec_hbm(prof, "c128")}
@@ -508,6 +513,54 @@ def pole_search(gsm, steps):
     return out
 
 
+# Fig. 4 of the paper: spherical air cavities in an n = 1.5 host on a
+# tetragonal lattice (Lambda_y = Lambda_z), filling factor 0.155 held fixed
+# while Lambda_x / Lambda_yz varies; its Maxwell-Garnett index, context
+FIG4_MG_INDEX = 1.4213
+
+
+def fresnel_tensor(gsm, steps):
+    """The paper's tensor retrieval on Fig. 4's uniaxial lattices: cavity
+    radius 0.03 lambda, f = 0.155, Lambda_x / Lambda_yz = 0.7 and 1.3
+    (analytic sphere images, 15^3 harmonics): the six axis pole searches
+    (N_p = 5, N_d = 10, complex64 + FP64 refinement to 1e-10) and the
+    diagonal Fresnel fit per lattice; wall time per tensor, the principal
+    indices (n_x extraordinary, n_y = n_z ordinary) and the fit's rms."""
+    import torch
+    M = (7, 7, 7)
+    lam, R, f = 1.0, 0.03, 0.155
+    out = {"unit": "tensors/s", "harmonics": "15^3", "cavity_radius_over_lambda": R, "fill": f,
+           "maxwell_garnett_index": FIG4_MG_INDEX, "rows": []}
+    plans = []
+    for rho in (0.7, 1.3):
+        lyz = (4.0 / 3.0 * np.pi * R ** 3 / (f * rho)) ** (1.0 / 3.0)
+        period = (rho * lyz, lyz, lyz)
+        sphere = {"kind": "sphere", "centre": tuple(0.5 * p for p in period), "size": R, "eps": 1.0}
+        plans.append((rho, period, gsm.Plan.from_shapes(period, 2.25, [sphere], M)))
+    opts = gsm.default_opts(tol=1e-10)
+    for _, _, plan in plans:                      # warm-up (grids, codelet tuning)
+        plan.fresnel_tensor(lam, M, 1.30, 1.55, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = {}
+    for _ in range(steps):
+        for rho, _, plan in plans:
+            res[rho] = plan.fresnel_tensor(lam, M, 1.30, 1.55, opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for rho, period, plan in plans:
+        eps, rms, pairs, _ = res[rho]
+        n = np.sqrt(np.diag(eps))
+        out["rows"].append({"lambda_x_over_lambda_yz": rho, "period_over_lambda": [round(p, 5) for p in period],
+                            "n_x": float(n[0]), "n_y": float(n[1]), "n_z": float(n[2]), "fit_rms": rms,
+                            "axis_index_pairs": pairs.tolist()})
+        plan.close()
+    n_t = len(plans) * steps
+    out["value"] = round(n_t / dt, 3)
+    out["ms_per_tensor"] = round(dt / n_t * 1e3, 3)
+    return out
+
+
 def hfield_solve(work, gsm, steps):
     """The headline batch (both bodies, 128 solves) through the H-field
     system of Eq.(5) (transverse H drives: the E drives rotated by k x),
@@ -750,6 +803,7 @@ def main():
     tab1 = table1(gsm, inputs, args.table1_reps) if args.table1_reps > 0 else None
     poles = pole_search(gsm, args.pole_steps) if args.pole_steps > 0 else None
     hfield = hfield_solve(work, gsm, args.hfield_steps) if args.hfield_steps > 0 else None
+    fresnel = fresnel_tensor(gsm, args.fresnel_steps) if args.fresnel_steps > 0 else None
     cpu = None if args.no_cpu else cpu_baseline(inputs)
     copy_bw = copy_bandwidth()
     per_step = total // args.steps
@@ -782,6 +836,7 @@ def main():
         "table1": tab1,
         "pole_search": poles,
         "hfield_solve": hfield,
+        "fresnel_tensor": fresnel,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
