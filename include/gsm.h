@@ -102,7 +102,7 @@ enum {
  * options), so repeated solves of one batch pay the capture once.  Results
  * are identical to those of separate launches.  BiCGStab steps are always
  * separate launches.  Off by default: on the MI355X with ROCm 7.2 the graph
- * launches ran 3-9 % slower than separate launches for these kernels. */
+ * launches ran 1-9 % slower than separate launches for these kernels. */
 /* gsm_apply modes: the E-field operator of Eq.(4) or its adjoint, or the
  * H-field operator of Eq.(5) */
 enum { GSM_APPLY_FORWARD = 0, GSM_APPLY_ADJOINT = 1, GSM_APPLY_FORWARD_H = 2 };
