@@ -18,6 +18,7 @@ that works on register arrays, so every twiddle is a literal constant.
 Usage: gen_fft.py OUT_HEADER
 """
 import math
+import struct
 import os
 import sys
 from fractions import Fraction
@@ -487,6 +488,17 @@ def twiddle_table(n):
     return f'__device__ constexpr double kTw{n}[{n}][2] = {{\n{body}\n}};\n'
 
 
+def _f32(x):
+    # the binary32 value nearest x (ties to even), written so that it parses back exactly
+    return repr(struct.unpack('f', struct.pack('f', x))[0]) + 'f'
+
+
+def twiddle_table_f32(n):
+    vals = [_cs(j, n) for j in range(n)]
+    body = ',\n'.join(f'  {{{_f32(c)}, {_f32(s)}}}' for c, s in vals)
+    return f'__device__ constexpr float kTw{n}f[{n}][2] = {{\n{body}\n}};\n'
+
+
 def dispatch(name, n, nin, nout, kind, param, family):
     return (f'template <> struct Codelet{kind}<{n}, {param}, {family}> {{\n'
             f'  template <typename T> __device__ static __forceinline__ void run('
@@ -523,6 +535,8 @@ def main(path):
     # every mixed size) for the others
     for n in (8, 16, 32, 64, 128, 512, 720):
         out.append(twiddle_table(n))
+    # complex64 copy of the order-512 roots, for twiddles indexed at run time
+    out.append(twiddle_table_f32(512))
     with open(path, 'w') as f:
         f.write('\n'.join(out))
     with open(os.path.join(os.path.dirname(path), 'fft_opcount.h'), 'w') as f:
