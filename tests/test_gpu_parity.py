@@ -79,6 +79,9 @@ OP_CASES = {
                    (12, 12, 12)),
     "sphere_m15": (lambda: inputs.sphere(64, 0.3, 4.0), (1, 1, 1), 1 / 0.3, (0, 0, 1), 1.0, (15, 15, 15)),
     "aniso_p128": (asym_body, (1.0, 0.9, 1.1), 1 / 0.4, (0.1, 0.2, 0.97), 1.0, (6, 5, 17)),
+    # every order of the 128-point z transforms (passes A and C in the
+    # four-step lane form, nothing folded away)
+    "full_z_p128": (asym_body, (1.0, 0.9, 1.1), 1 / 0.4, (0.1, -0.2, 0.97), 1.0, (3, 2, 31)),
     # P = 64 with different order counts per axis (rows and columns of the
     # plane pass cropped differently, Mx < My and Mx > My)
     "aniso_p64": (asym_body, (1.0, 0.9, 1.1), 1 / 0.35, (0.2, -0.3, 0.93), 1.0, (9, 14, 11)),
